@@ -1,0 +1,114 @@
+"""Pins of the oracle's Hamiltonian, commutator and integrator against closed
+forms (no self-interaction or homogeneous data):
+
+* homogeneous in z with mu = 0: every cell precesses, dP/dt = B x P with
+  B = omega (sin 2th, 0, -cos 2th) + lambda z_hat for neutrinos and
+  omega (sin 2th, 0, -cos 2th) - lambda z_hat for the antineutrino's own
+  vector; one RK4 step of a linear ODE is exactly the degree-4 Taylor
+  polynomial of exp(dt A), so P^n = R^n P^0;
+* the continuum vacuum-oscillation solution eq:vac_sols (Sec. 4.2) for a
+  pure nu_e packet moving at v = 0.5, and the minimum survival probability
+  the paper states for omega = 0.1, theta = 37 degrees (golden fixture);
+* homogeneous data with self-interaction: |P| of every bin is conserved by
+  the exact flow, so the RK4 drift must fall as dt^4.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+from paper_2203_12866_amd import workloads as wl
+from tests.golden.fixtures import key_values
+
+
+def pvec(y, base):
+    """(P0, P1, P2, P3) of rho = (P0 + P.sigma)/2 from the planes."""
+    ee, xx, re, im = y[base], y[base + 1], y[base + 2], y[base + 3]
+    return np.stack([ee + xx, 2 * re, -2 * im, ee - xx])
+
+
+def cross_matrix(b):
+    return np.array([[0, -b[2], b[1]], [b[2], 0, -b[0]], [-b[1], b[0], 0]])
+
+
+def rk4_linear_propagator(A, dt):
+    hA = dt * A
+    R = np.eye(3)
+    term = np.eye(3)
+    for n in range(1, 5):
+        term = term @ hA / n
+        R = R + term
+    return R
+
+
+@pytest.mark.parametrize("scheme", [o.FD_KO, o.FV_WENO7])
+def test_homogeneous_precession_rk4_closed_form(scheme):
+    nz, nv, L = 12, 6, 10.0
+    omega, theta, lam, dt, steps = 0.7, 0.61, 0.45, 0.13, 40
+    cell = wl.random_unit_state(1, nv, seed=21)
+    y0 = np.ascontiguousarray(np.repeat(cell, nz, axis=1))  # same in every z row
+    p = o.Problem(nz=nz, nv=nv, L=L, dt=dt, mu=0.0, omega=omega, theta=theta, lam=lam, alpha=0.9,
+                  scheme=scheme, g_nu=np.ones(nv), g_nubar=np.ones(nv))
+    y = o.rk4(p, y0, steps)
+    Bvac = omega * np.array([math.sin(2 * theta), 0.0, -math.cos(2 * theta)])
+    for base, B in ((0, Bvac + lam * np.array([0, 0, 1.0])), (4, Bvac - lam * np.array([0, 0, 1.0]))):
+        R = np.linalg.matrix_power(rk4_linear_propagator(cross_matrix(B), dt), steps)
+        P0 = pvec(y0, base)
+        P = pvec(y, base)
+        np.testing.assert_allclose(P[0], P0[0], rtol=0, atol=1e-13)
+        expect = np.einsum("ab,bzv->azv", R, P0[1:])
+        np.testing.assert_allclose(P[1:], expect, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("scheme", [o.FD_KO, o.FV_WENO7])
+def test_vacuum_oscillation_matches_eq_vac_sols(scheme):
+    g = key_values("vacuum_oscillation.txt")
+    omega, theta, v = g["omega"], g["theta_deg"] * math.pi / 180.0, g["v"]
+    nz, nv, L = 2000, 2, 200.0           # the paper's Nz; bins at v = -0.5 and v = +0.5
+    dz = L / nz
+    dt = 0.2 * dz / 0.5
+    steps = int(round(math.pi / omega / dt))  # half a vacuum period: the minimum of <rho_ee>
+    z = o.positions(nz, L)
+    prof = np.exp(-z ** 2 / (2 * 5.0 ** 2))
+    y0 = np.zeros((8, nz, nv))
+    y0[0, :, 1] = prof                      # pure nu_e packet in the v = +0.5 bin
+    p = o.Problem(nz=nz, nv=nv, L=L, dt=dt, mu=0.0, omega=omega, theta=theta, lam=0.0, alpha=0.9,
+                  scheme=scheme, g_nu=np.ones(nv), g_nubar=np.ones(nv))
+    y = o.rk4(p, y0, steps)
+    t = steps * dt
+    shifted = np.exp(-(z - v * t) ** 2 / (2 * 5.0 ** 2))
+    s2, c2 = math.sin(2 * theta), math.cos(2 * theta)
+    sn2 = math.sin(omega * t / 2) ** 2
+    expect = {
+        0: shifted * (1 - s2 ** 2 * sn2),
+        1: shifted * (s2 ** 2 * sn2),
+        2: -shifted * (s2 * c2 * sn2),
+        3: shifted * 0.5 * s2 * math.sin(omega * t),
+    }
+    for c, ex in expect.items():
+        e2 = math.sqrt(np.mean((y[c, :, 1] - ex) ** 2))  # E_2 of eq:E2
+        assert e2 < 1e-6, (c, e2)
+    surv = y[0, :, 1].sum() / y0[0, :, 1].sum()
+    assert abs(surv - (1 - s2 ** 2 * sn2)) < 1e-6
+    # the value the paper prints for these parameters
+    assert abs(surv - g["min_survival"]) < 0.5 * 10 ** (-g["min_survival_digits"])
+
+
+def test_homogeneous_self_interaction_conserves_polarisation_length_to_fourth_order():
+    nz, nv, L = 9, 8, 9.0
+    cell = wl.random_unit_state(1, nv, seed=5)
+    y0 = np.ascontiguousarray(np.repeat(cell, nz, axis=1))
+    T = 4.0
+    drift = []
+    for dt in (0.02, 0.01):
+        p = o.Problem(nz=nz, nv=nv, L=L, dt=dt, mu=1.0, omega=0.1, theta=0.3, lam=0.2, alpha=0.8,
+                      scheme=o.FD_KO, g_nu=o.angular_dist(nv, 0.6), g_nubar=o.angular_dist(nv, 0.5))
+        y = o.rk4(p, y0, int(round(T / dt)))
+        d = 0.0
+        for base in (0, 4):
+            P = pvec(y, base)
+            d = max(d, np.abs(np.sqrt((P[1:] ** 2).sum(axis=0)) - 1.0).max())
+        drift.append(d)
+    assert drift[0] > 1e-12
+    assert abs(math.log2(drift[0] / drift[1]) - 4.0) < 0.3, drift
