@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the RK4 hot path on one MI355X.
+
+A "step" is one classic RK4 step (4 stage launches) over the whole grid of
+the workload; the metric is cell-velocity-stage updates per second
+(nz * nv * 4 per step) plus the HBM bandwidth those updates imply.  The
+default workload is FD + Kreiss-Oliger on 16384 x 128 cells (L = 1600,
+ELN-crossing Gaussian family, alpha drawn from the seed), run in the
+FP32-with-FP64-accumulation form (headline) and in the FP64 form.
+
+Output: one JSON line on stdout.  Inputs are resident in HBM before the
+timed region starts.  --gpus N with N > 1 exits: this build runs one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell·v·stage updates/s + HBM GB/s, FP32 vs FP64 at stated error vs oracle"
+PEAK_HBM_GBPS = 8000.0
+WORKLOADS = {
+    "fd_ko_16384x128": lambda prec: __import__("paper_2203_12866_amd.workloads", fromlist=["x"]).fd_16384x128(2, prec),
+    "fv_weno7_65536x256": lambda prec: __import__("paper_2203_12866_amd.workloads", fromlist=["x"]).fv_65536x256(3, prec),
+    "fd_ko_512x32": lambda prec: dict(__import__("paper_2203_12866_amd.workloads", fromlist=["x"]).small_fd(1), precision=prec),
+}
+FORMS = {"fp32acc": 1, "fp64": 0}
+KERNEL_SOURCES = ("paper_2203_12866_amd/csrc/stage_kernels.hip",)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, form: str):
+    """HBM bytes per stage launch from the committed rocprofv3 counter summary,
+    or None if it is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash():
+        return None
+    e = t.get("entries", {}).get(f"{workload}/{form}")
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def run_form(cosenu, torch, w, steps, warmup, seg, stage_steps):
+    sim = cosenu.Sim(w)
+    sim.bind_torch_stream()
+    chosen = sim.autotune() if seg is None else seg
+    if seg is not None:
+        sim.set_seg_rows(seg)
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev_ms = sim.time_steps(steps)           # HIP events around the K steps, then waits
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms = sim.time_stages(stage_steps)  # one event pair around every stage launch
+    info = sim.info()
+    state = sim.get_state()
+    sim.close()
+    cells = w["nz"] * w["nv"]
+    launch_s = sum(stage_ms) / (4.0 * stage_steps) / 1e3
+    return dict(seg=chosen, wall=wall, ev_ms=ev_ms, stage_ms=stage_ms, info=info, state=state,
+                updates=cells * 4.0 * steps / wall,
+                gbps_model=info["bytes_per_step"] * steps / wall / 1e9,
+                launch_s=launch_s,
+                achieved_gbps=info["bytes_per_step"] / 4.0 / launch_s / 1e9)
+
+
+def cpu_baseline(cosenu, w, budget_s):
+    """The FP64 oracle on the same grid (bounded sample of whole RK4 steps),
+    and the FP64 GPU form's error against it after the same steps."""
+    import numpy as np
+    from oracle import oracle
+    p = oracle.problem_from_workload(w)
+    y0 = oracle.initial_state_for(w)
+    t0 = time.perf_counter()
+    y = oracle.rk4(p, y0, 1)
+    one = time.perf_counter() - t0
+    n = max(1, min(20, int(budget_s / max(one, 1e-9))))
+    t1 = time.perf_counter()
+    if n > 1:
+        y = oracle.rk4(p, y, n - 1)
+    total = one + (time.perf_counter() - t1)
+    errs = {}
+    for form, prec in FORMS.items():
+        with cosenu.Sim(dict(w, precision=prec)) as s:
+            s.step(n)
+            g = s.get_state()
+        if prec == 0:
+            errs[form] = {"max_abs": float(np.abs(g - y).max())}
+        else:
+            errs[form] = {"max_abs": float(np.abs(g - y).max()),
+                          "max_rel_offdiag": float(np.abs(g[2:4] - y[2:4]).max() / np.abs(y[2:4]).max())}
+    cells = w["nz"] * w["nv"]
+    return ({"value": cells * 4.0 * n / total, "unit": "cell·v·stage updates/s",
+             "cores": oracle.num_threads(), "kind": "oracle",
+             "sample": f"{n} RK4 step(s) of the full {w['nz']}x{w['nv']} grid from the initial state, FP64 oracle "
+                       f"(O(nv) self-interaction sum per cell, OpenMP over z), {total:.1f} s"},
+            {"steps": n, "vs_oracle": errs})
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="fd_ko_16384x128", choices=sorted(WORKLOADS))
+    ap.add_argument("--seg-rows", type=int, default=None, help="fixed launch shape (default: autotune)")
+    ap.add_argument("--stage-steps", type=int, default=50, help="steps timed launch by launch for the roofline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU (z-sharded) execution is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2203_12866_amd import cosenu
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    mk = WORKLOADS[args.workload]
+    res = {}
+    for form, prec in FORMS.items():
+        res[form] = run_form(cosenu, torch, mk(prec), args.steps, args.warmup, args.seg_rows, args.stage_steps)
+        print(f"[bench] {args.workload} {form}: {res[form]['updates']:.4e} upd/s, "
+              f"{res[form]['gbps_model']:.0f} GB/s modelled, seg {res[form]['seg']}", file=sys.stderr, flush=True)
+
+    head = res["fp32acc"]
+    w = mk(1)
+    a, b = res["fp32acc"]["state"], res["fp64"]["state"]
+    fp32_vs_fp64 = {
+        "max_abs": float(np.abs(a - b).max()),
+        "max_rel_offdiag": float(np.abs(a[2:4] - b[2:4]).max() / max(np.abs(b[2:4]).max(), 1e-300)),
+    }
+    out = {
+        "metric": METRIC,
+        "value": head["updates"],
+        "unit": "cell·v·stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["wall"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64acc",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "nz": w["nz"], "nv": w["nv"], "L": w["L"], "cfl": w["cfl"],
+                   "scheme": "FD+KO" if w["scheme"] == 0 else "FV+WENO7", "alpha": w["alpha"],
+                   "omega": w["omega"], "lambda": w["lam"], "form": "FP32 stencils, FP64 moments/commutator/RK4",
+                   "seg_rows": head["seg"]},
+        "hbm_gbps": head["gbps_model"],
+        "bytes_per_update": head["info"]["bytes_per_step"] / (w["nz"] * w["nv"] * 4.0),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": head["achieved_gbps"],
+            "peak": PEAK_HBM_GBPS,
+            "unit": "GB/s",
+            "frac": head["achieved_gbps"] / PEAK_HBM_GBPS,
+            "traffic": measured_traffic(args.workload, "fp32acc"),
+            "kernel": "stage_kernel<FD,FP32acc>" if w["scheme"] == 0 else "stage_kernel<WENO7,FP32acc>",
+            "avg_launch_us": head["launch_s"] * 1e6,
+        },
+        "fp64_form": {
+            "value": res["fp64"]["updates"],
+            "ms_per_step": res["fp64"]["wall"] * 1e3 / args.steps,
+            "hbm_gbps": res["fp64"]["gbps_model"],
+            "bytes_per_update": res["fp64"]["info"]["bytes_per_step"] / (w["nz"] * w["nv"] * 4.0),
+            "roofline_achieved_gbps": res["fp64"]["achieved_gbps"],
+            "roofline_frac": res["fp64"]["achieved_gbps"] / PEAK_HBM_GBPS,
+            "avg_launch_us": res["fp64"]["launch_s"] * 1e6,
+            "seg_rows": res["fp64"]["seg"],
+        },
+        "fp32_speedup_over_fp64": head["updates"] / res["fp64"]["updates"],
+        "fp32_vs_fp64_after_run": fp32_vs_fp64,
+    }
+    if not args.no_cpu_baseline:
+        cb, errs = cpu_baseline(cosenu, mk(0), args.cpu_budget)
+        out["cpu_baseline"] = cb
+        out["error_vs_oracle"] = errs
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

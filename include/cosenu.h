@@ -1,0 +1,217 @@
+/*
+ * cosenu.h -- C ABI of the MI355X (gfx950) hot path of the COSEnu
+ * collective-oscillation solver (George, Lin, Wu, Liu, Xiong,
+ * arXiv:2203.12866).
+ *
+ * The library advances the two-flavour quantum kinetic equations of Sec. 2
+ * (eq:eom),
+ *     (d/dt + v d/dz) rho    = -i [H,    rho   ],
+ *     (d/dt + v d/dz) rhobar = -i [Hbar, rhobar],
+ * with H = H_vac + H_m + H_nunu and Hbar = H_vac - H_m + Hbar_nunu (eq:ham),
+ * on a periodic z grid times a grid of velocity bins v in [-1, 1] (Sec. 3),
+ * by the method of lines with classic fourth-order Runge-Kutta.  Advection is
+ * either the fourth-order central finite difference with Kreiss-Oliger
+ * dissipation (Sec. 3.1) or the finite-volume update eq:cell_av with WENO7
+ * interface fluxes (Sec. 3.2, Appendix A).
+ *
+ * Conventions common to every entry point:
+ *  - Return value 0 on success, a negative COSENU_E* code on failure; no C++
+ *    exception crosses the ABI.  cosenu_strerror() names a code and
+ *    cosenu_last_error() gives the detail recorded on a handle.
+ *  - The caller owns every host buffer passed in; the library owns every
+ *    device buffer it allocates (freed by the matching destroy call).
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - cosenu_step / cosenu_batch_step are asynchronous on the handle's HIP
+ *    stream; every call that returns host data synchronises that stream.
+ *  - State arrays on the host are FP64, shape [8][nz][nv] with v fastest,
+ *    component order c = 0 rho_ee, 1 rho_xx, 2 Re rho_ex, 3 Im rho_ex,
+ *    4 rhobar_ee, 5 rhobar_xx, 6 Re rhobar_ex, 7 Im rhobar_ex
+ *    (the density matrices of eq:rho, after the rescaling rho -> g rho of
+ *    Sec. 5, i.e. the angular weight g(v) is not folded into the state).
+ */
+#ifndef COSENU_H
+#define COSENU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define COSENU_OK 0
+#define COSENU_EINVAL (-1)     /* a parameter is out of range or a buffer is too small */
+#define COSENU_ENOMEM (-2)     /* device or host allocation failed                      */
+#define COSENU_EDEVICE (-3)    /* a HIP runtime call failed (detail: cosenu_last_error)  */
+#define COSENU_ENONFINITE (-4) /* a diagnostics call found NaN or Inf in the state       */
+#define COSENU_ESTATE (-5)     /* misuse: null handle, call out of order                 */
+
+/* ---- discretisations and arithmetic forms -------------------------------- */
+enum cosenu_scheme {
+    COSENU_FD_KO = 0,    /* FD4 central advection + Kreiss-Oliger r = 2 (Sec. 3.1)      */
+    COSENU_FV_WENO7 = 1  /* finite volume eq:cell_av, WENO7 fluxes of f = v u (Sec. 3.2) */
+};
+enum cosenu_precision {
+    COSENU_FP64 = 0,       /* everything in FP64                                          */
+    COSENU_FP32_ACC64 = 1  /* advection stencils and WENO in FP32 on FP32-rounded stage
+                              values; angular moments, commutators, flux differences and
+                              the Runge-Kutta accumulation of the state in FP64           */
+};
+
+typedef struct cosenu_sim cosenu_sim;
+typedef struct cosenu_batch cosenu_batch;
+
+/* Problem description (Sec. 2, 3 and 5).  Units: 1/mu for t and z.
+ *  nz, nv      number of z cells (periodic) and velocity bins; nz >= 5 for FD,
+ *              nz >= 9 for WENO7; nv >= 1.  Bins are midpoints
+ *              v_j = -1 + (j + 1/2) * 2/nv; the velocity integral of eq:ham is
+ *              the Riemann sum over them (Sec. 3).
+ *  L           domain length; cells are centred at z_i = -L/2 + (i + 1/2) L/nz.
+ *  cfl         dt = cfl * dz / max_j |v_j|  (Sec. 3); 0 < cfl <= 2.
+ *  mu          self-interaction strength of eq:ham.
+ *  omega,theta vacuum frequency and mixing angle (radians) of H_vac (Sec. 2).
+ *  lambda      matter potential: H_m = diag(lambda, 0), Hbar_m = -diag(lambda, 0)
+ *              (the paper removes H_m by a frame rotation, Sec. 2 footnote).
+ *  alpha       n_nubar / n_nu (Sec. 5).
+ *  sigma_nu, sigma_nubar  widths of g(v) ~ exp(-(v-1)^2 / 2 sigma^2), each
+ *              normalised so that sum_j dv g_j = 1 (Sec. 5).
+ *  pert_amp, pert_width, phase   initial data eqs:perts with
+ *              eps(z) = pert_amp * exp(-z^2 / pert_width), identical in every
+ *              bin; rho_ex = eps/2 e^{i phase}, rhobar_ex = eps/2 e^{-i phase}
+ *              (phase = 0 is the paper's data).
+ *  ko_eps      Kreiss-Oliger strength (paper: 0.1), FD only.
+ *  weno_eps    WENO regulator of eq:weight (paper: about 1e-6), WENO7 only.  */
+typedef struct {
+    int32_t nz, nv;
+    int32_t scheme;    /* enum cosenu_scheme    */
+    int32_t precision; /* enum cosenu_precision */
+    double L, cfl;
+    double mu, omega, theta, lambda;
+    double alpha, sigma_nu, sigma_nubar;
+    double pert_amp, pert_width, phase;
+    double ko_eps, weno_eps;
+} cosenu_params;
+
+/* Conserved quantities and error measures of Sec. 5, from the current state.
+ *  M0[4]     dz dv sum (g P - alpha gbar Pbar~) as (trace, x, y, z) where
+ *            rho = (P0 + P.sigma)/2 and Pbar~ is the vector of rhobar^*; M0[3]
+ *            is the net lepton number of Sec. 5.
+ *  N_nu, N_nubar   dz dv sum g Tr rho, dz dv sum gbar Tr rhobar.
+ *  dP_max    max over cells and species of | |P| - 1 |.
+ *  dP_mean   sum g | |P_nu| - 1 | / sum g (g-weighted mean over all cells).
+ *  ee_nu, ee_nubar   dz dv sum g rho_ee, dz dv sum gbar rhobar_ee.
+ *  Pee_nu, Pee_nubar survival probabilities: ee_* divided by its value at the
+ *            last cosenu_create / cosenu_set_state (Sec. 4.2, taken g-weighted).
+ *  B_dot_M0  (sin 2theta, 0, -cos 2theta) . M0[1..3].
+ *  nonfinite number of NaN / Inf values found in the state.                 */
+typedef struct {
+    double t;
+    int64_t step;
+    double M0[4];
+    double N_nu, N_nubar;
+    double dP_max, dP_mean;
+    double ee_nu, ee_nubar;
+    double Pee_nu, Pee_nubar;
+    double B_dot_M0;
+    int64_t nonfinite;
+} cosenu_conserved_t;
+
+/* Read-only facts about a handle. */
+typedef struct {
+    double dt, dz, dv, t;
+    int64_t step;
+    size_t device_bytes;     /* device memory owned by the handle              */
+    int32_t seg_rows;        /* z rows marched by one lane group (launch shape) */
+    int32_t lanes_per_row;   /* lanes sharing one z row (power of two <= 64)   */
+    int32_t v_chunks;        /* 64-bin chunks per row (1 when nv <= 64)        */
+    int32_t blocks_per_stage;/* workgroups of one stage launch                 */
+    double bytes_per_step;   /* algorithmic HBM bytes of one RK4 step          */
+} cosenu_info_t;
+
+/* Fills *p with the paper's fiducial values (Sec. 5): nz = 512, nv = 32,
+ * L = 400, cfl = 0.4, mu = 1, omega = lambda = 0, theta = 37 deg,
+ * alpha = 0.9, sigma = 0.6 / 0.5, eps(z) = 1e-6 exp(-z^2/50), FD + KO with
+ * ko_eps = 0.1, weno_eps = 1e-6, FP64.  Returns COSENU_EINVAL if p is NULL. */
+int cosenu_params_default(cosenu_params *p);
+
+/* Validates *p, allocates the device state on the current HIP device,
+ * builds the initial data of eqs:perts, uploads it and prepares the step
+ * graph.  On success *out owns everything; on failure *out is NULL. */
+int cosenu_create(const cosenu_params *p, cosenu_sim **out);
+void cosenu_destroy(cosenu_sim *s);
+
+/* Enqueues nsteps RK4 steps (4 stage launches each) on the handle's stream;
+ * returns without waiting.  nsteps = 0 is a no-op; nsteps < 0 is EINVAL. */
+int cosenu_step(cosenu_sim *s, int64_t nsteps);
+/* Waits for everything enqueued on the handle's stream. */
+int cosenu_sync(cosenu_sim *s);
+
+/* Copies the FP64 state [8][nz][nv] to / from the host.  n is the number of
+ * doubles in the caller's buffer (must be >= 8*nz*nv).  set_state also
+ * recomputes the angular moments of the new state and makes it the reference
+ * of the survival probabilities; t and step are left unchanged. */
+int cosenu_get_state(cosenu_sim *s, double *out, size_t n);
+int cosenu_set_state(cosenu_sim *s, const double *in, size_t n);
+/* Sets the simulation clock (used with set_state to resume a checkpoint). */
+int cosenu_set_clock(cosenu_sim *s, double t, int64_t step);
+
+/* Angular moments of D = g rho - alpha gbar rhobar^* of the current state,
+ * per z row: out[(z*2 + m)*4 + q], m = 0: dv sum_j D_j, m = 1: dv sum_j v_j D_j,
+ * q = 0 D_ee, 1 D_xx, 2 Re D_ex, 3 Im D_ex (eq:ham is H_nunu(v) = mu (m0 - v m1)).
+ * n must be >= 8*nz.  FP64. */
+int cosenu_moments(cosenu_sim *s, double *out, size_t n);
+
+/* Conserved quantities of the current state (FP64 reductions in a fixed
+ * order).  Returns COSENU_ENONFINITE (with *out filled) if NaN/Inf found. */
+int cosenu_conserved(cosenu_sim *s, cosenu_conserved_t *out);
+
+int cosenu_info(cosenu_sim *s, cosenu_info_t *out);
+
+/* Makes the handle enqueue its work on an existing HIP stream (for example
+ * torch.cuda.current_stream().cuda_stream).  NULL restores the handle's own
+ * stream.  The caller keeps ownership of the stream. */
+int cosenu_set_stream(cosenu_sim *s, void *hip_stream);
+
+/* Launch shape: z rows per lane group (>= 1).  0 restores the tuned default.
+ * Results do not depend on it (bitwise). */
+int cosenu_set_seg_rows(cosenu_sim *s, int32_t seg_rows);
+
+/* Times nsteps steps on the handle's stream with HIP events (after the work
+ * already queued) and returns the elapsed milliseconds; synchronises. */
+int cosenu_time_steps(cosenu_sim *s, int64_t nsteps, double *ms);
+/* Times each stage kernel separately over nsteps steps (eagerly launched,
+ * one event pair around each launch); ms_stage[4] receives the summed
+ * milliseconds of stage 1..4.  Synchronises. */
+int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage);
+
+/* Picks seg_rows by timing candidate launch shapes on scratch buffers of
+ * the handle's shape (the state is not modified); results are cached per
+ * (scheme, precision, nv, nz bucket) for the process.  *seg_rows receives
+ * the choice (may be NULL). */
+int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows);
+
+const char *cosenu_strerror(int code);
+const char *cosenu_last_error(const cosenu_sim *s);
+
+/* ---- batched execution ----------------------------------------------------
+ * n independent simulations of any sizes and schemes (one precision for the
+ * whole batch, taken from p[0]) advanced together: every RK4 stage of every
+ * instance is one persistent kernel launch walking a work list, and a step
+ * of the whole batch is one HIP graph.  Instance i behaves exactly like a
+ * cosenu_sim created from p[i] with the same launch shape.                  */
+int cosenu_batch_create(const cosenu_params *p, int32_t n, cosenu_batch **out);
+void cosenu_batch_destroy(cosenu_batch *b);
+int cosenu_batch_step(cosenu_batch *b, int64_t nsteps);
+int cosenu_batch_sync(cosenu_batch *b);
+int cosenu_batch_get_state(cosenu_batch *b, int32_t i, double *out, size_t n);
+int cosenu_batch_set_state(cosenu_batch *b, int32_t i, const double *in, size_t n);
+int cosenu_batch_conserved(cosenu_batch *b, int32_t i, cosenu_conserved_t *out);
+int cosenu_batch_info(cosenu_batch *b, int32_t i, cosenu_info_t *out);
+int cosenu_batch_time_steps(cosenu_batch *b, int64_t nsteps, double *ms);
+const char *cosenu_batch_last_error(const cosenu_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COSENU_H */

@@ -1,0 +1,658 @@
+// Host runtime behind the C ABI of include/cosenu.h: parameter checks, grid
+// and initial data (Sec. 3 and 5), device buffers, the per-step HIP graph,
+// diagnostics, timing and the launch-shape autotuner.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "cosenu.h"
+#include "cosenu_host.h"
+#include "cosenu_internal.h"
+
+using namespace cosenu;
+
+namespace cosenu {
+
+const char *strerror_code(int code) {
+    switch (code) {
+        case COSENU_OK: return "ok";
+        case COSENU_EINVAL: return "invalid argument";
+        case COSENU_ENOMEM: return "out of memory";
+        case COSENU_EDEVICE: return "HIP device error";
+        case COSENU_ENONFINITE: return "non-finite values in the state";
+        case COSENU_ESTATE: return "invalid handle or call order";
+        default: return "unknown error";
+    }
+}
+
+std::string validate_params(const cosenu_params &p) {
+    char buf[256];
+    auto fin = [](double x) { return std::isfinite(x); };
+    if (p.scheme != COSENU_FD_KO && p.scheme != COSENU_FV_WENO7) return "scheme must be COSENU_FD_KO or COSENU_FV_WENO7";
+    if (p.precision != COSENU_FP64 && p.precision != COSENU_FP32_ACC64) return "precision must be COSENU_FP64 or COSENU_FP32_ACC64";
+    const int nzmin = p.scheme == COSENU_FD_KO ? 5 : 9;
+    if (p.nz < nzmin) {
+        snprintf(buf, sizeof buf, "nz = %d is below the stencil width (%d)", p.nz, nzmin);
+        return buf;
+    }
+    if (p.nv < 2) return "nv must be >= 2 (with one bin max|v| = 0 and dt is undefined)";
+    if ((double)p.nz * (double)p.nv > 4.0e9) return "nz * nv too large";
+    if (!(fin(p.L) && p.L > 0)) return "L must be finite and > 0";
+    if (!(fin(p.cfl) && p.cfl > 0 && p.cfl <= 2.0)) return "cfl must be in (0, 2]";
+    if (!(fin(p.mu) && fin(p.omega) && fin(p.theta) && fin(p.lambda))) return "mu, omega, theta, lambda must be finite";
+    if (!(fin(p.alpha) && p.alpha >= 0)) return "alpha must be finite and >= 0";
+    if (!(fin(p.sigma_nu) && p.sigma_nu > 0 && fin(p.sigma_nubar) && p.sigma_nubar > 0)) return "sigmas must be > 0";
+    if (!(fin(p.pert_amp) && std::fabs(p.pert_amp) <= 1.0)) return "|pert_amp| must be <= 1";
+    if (!(fin(p.pert_width) && p.pert_width > 0)) return "pert_width must be > 0";
+    if (!fin(p.phase)) return "phase must be finite";
+    if (!(fin(p.ko_eps) && p.ko_eps >= 0)) return "ko_eps must be >= 0";
+    if (!(fin(p.weno_eps) && p.weno_eps > 0)) return "weno_eps must be > 0";
+    return "";
+}
+
+// Bin midpoints v_j = -1 + (j + 1/2) dv (Sec. 3).
+std::vector<double> bin_velocities(int nv) {
+    std::vector<double> v(nv);
+    const double dv = 2.0 / nv;
+    for (int j = 0; j < nv; ++j) v[j] = -1.0 + (j + 0.5) * dv;
+    return v;
+}
+
+// g(v) ~ exp(-(v-1)^2 / 2 sigma^2) with sum_j dv g_j = 1 (Sec. 5).
+std::vector<double> gaussian_distribution(int nv, double sigma) {
+    std::vector<double> v = bin_velocities(nv), g(nv);
+    const double dv = 2.0 / nv;
+    double s = 0.0;
+    for (int j = 0; j < nv; ++j) {
+        g[j] = std::exp(-(v[j] - 1.0) * (v[j] - 1.0) / (2.0 * sigma * sigma));
+        s += g[j] * dv;
+    }
+    for (int j = 0; j < nv; ++j) g[j] /= s;
+    return g;
+}
+
+double time_step(const cosenu_params &p) {
+    const double dv = 2.0 / p.nv;
+    const double vmax = 1.0 - 0.5 * dv;  // largest |midpoint|
+    return p.cfl * (p.L / p.nz) / vmax;
+}
+
+// eqs:perts: eps(z) = amp exp(-z^2/width), pure flavour states of |P| = 1,
+// rho_ex = eps/2 e^{i phase}, rhobar = rho^*.
+void initial_state(const cosenu_params &p, std::vector<double> &y) {
+    const size_t plane = (size_t)p.nz * p.nv;
+    y.assign(8 * plane, 0.0);
+    const double dz = p.L / p.nz, c = std::cos(p.phase), s = std::sin(p.phase);
+    for (int i = 0; i < p.nz; ++i) {
+        const double z = -0.5 * p.L + (i + 0.5) * dz;
+        const double e = p.pert_amp * std::exp(-z * z / p.pert_width);
+        const double r = std::sqrt(1.0 - e * e);
+        const double vals[8] = {0.5 * (1.0 + r), 0.5 * (1.0 - r), 0.5 * e * c, 0.5 * e * s,
+                                0.5 * (1.0 + r), 0.5 * (1.0 - r), 0.5 * e * c, -0.5 * e * s};
+        for (int cc = 0; cc < 8; ++cc) {
+            double *row = &y[cc * plane + (size_t)i * p.nv];
+            for (int j = 0; j < p.nv; ++j) row[j] = vals[cc];
+        }
+    }
+}
+
+int lr_log2_for(int nv) {
+    int lr = 1, lg = 0;
+    const int want = std::min(nv, kWave);
+    while (lr < want) { lr <<= 1; ++lg; }
+    return lg;
+}
+
+int default_seg_rows(int nz, int nv) {
+    const int lg = lr_log2_for(nv);
+    const int G = kWave >> lg;
+    const int vch = nv > kWave ? (nv + kWave - 1) / kWave : 1;
+    // aim at ~2048 waves per stage launch, segments of 4 .. 64 rows
+    long long target = (long long)nz * vch / ((long long)G * 2048);
+    int s = 4;
+    while (s * 2 <= target && s < 64) s *= 2;
+    return s;
+}
+
+void set_shape(InstDesc &d, int seg) {
+    d.seg = std::max(1, std::min(seg, d.nz));
+    d.nseg = (d.nz + d.seg - 1) / d.seg;
+    d.ntasks = d.nseg * d.vchunks;
+}
+
+double bytes_per_cell_step(int form) {
+    // 12 FP64 streams of 8 components; in the FP32 form Y3 is written and read in FP32
+    return form == COSENU_FP64 ? 12.0 * 64.0 : 10.0 * 64.0 + 2.0 * 32.0;
+}
+
+void fill_desc_constants(const cosenu_params &p, InstDesc &d) {
+    std::memset(&d, 0, sizeof d);
+    d.nz = p.nz;
+    d.nv = p.nv;
+    d.scheme = p.scheme;
+    d.form = p.precision;
+    d.lr_log2 = lr_log2_for(p.nv);
+    d.vchunks = p.nv > kWave ? (p.nv + kWave - 1) / kWave : 1;
+    d.dz_inv = p.nz / p.L;
+    d.dt = time_step(p);
+    d.dv = 2.0 / p.nv;
+    d.mudv = p.mu * d.dv;
+    d.h3vac = -p.omega * std::cos(2.0 * p.theta);
+    d.hexvac = 0.5 * p.omega * std::sin(2.0 * p.theta);
+    d.lam = p.lambda;
+    d.ko16 = p.ko_eps / 16.0;
+    d.weno_eps = p.weno_eps;
+    set_shape(d, default_seg_rows(p.nz, p.nv));
+}
+
+// Sum of the per-task diagnostic partials (task order) into the public struct.
+void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vector<double> &part, double ee0n,
+                      double ee0b, double t, int64_t step, cosenu_conserved_t *out) {
+    double a[kDiagQ] = {0};
+    for (int task = 0; task < d.ntasks; ++task) {
+        const double *q = &part[(size_t)task * kDiagQ];
+        for (int k = 0; k < kDiagQ; ++k) {
+            if (k == 10) a[k] = std::max(a[k], q[k]);
+            else a[k] += q[k];
+        }
+    }
+    const double cell = (p.L / p.nz) * d.dv;
+    std::memset(out, 0, sizeof *out);
+    out->t = t;
+    out->step = step;
+    for (int k = 0; k < 4; ++k) out->M0[k] = cell * a[k];
+    out->N_nu = cell * a[4];
+    out->N_nubar = cell * a[5];
+    out->dP_mean = a[7] > 0 ? a[6] / a[7] : 0.0;
+    out->dP_max = a[10];
+    out->ee_nu = cell * a[8];
+    out->ee_nubar = cell * a[9];
+    out->Pee_nu = ee0n != 0 ? out->ee_nu / ee0n : 0.0;
+    out->Pee_nubar = ee0b != 0 ? out->ee_nubar / ee0b : 0.0;
+    out->B_dot_M0 = std::sin(2.0 * p.theta) * out->M0[1] - std::cos(2.0 * p.theta) * out->M0[3];
+    out->nonfinite = (int64_t)a[11];
+}
+
+// Launch-shape cache shared by single instances and batches.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune_cache;
+
+int tuned_seg(int scheme, int form, int nz, int nv) {
+    int bucket = 0;
+    while ((1 << (bucket + 1)) <= nz) ++bucket;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(std::make_tuple(scheme, form, nv, bucket));
+    return it == g_tune_cache.end() ? 0 : it->second;
+}
+
+void store_tuned_seg(int scheme, int form, int nz, int nv, int seg) {
+    int bucket = 0;
+    while ((1 << (bucket + 1)) <= nz) ++bucket;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[std::make_tuple(scheme, form, nv, bucket)] = seg;
+}
+
+}  // namespace cosenu
+
+// ---------------------------------------------------------------------------
+struct cosenu_sim {
+    cosenu_params prm;
+    InstDesc d;
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    hipGraphExec_t g1 = nullptr, gN = nullptr;
+    int gN_steps = 16;
+    bool graphs_ok = false;
+    double t = 0.0;
+    int64_t step = 0;
+    double ee0_nu = 0.0, ee0_nubar = 0.0;
+    size_t bytes = 0;
+    std::vector<void *> allocs;
+    double *diag_part = nullptr;   // [max tasks][kDiagQ]
+    size_t diag_cap = 0;           // in tasks
+    double *mom_out = nullptr;     // [nz][vchunks][8]
+    std::string err;
+};
+
+#define SIM_CHECK(s)                                   \
+    do {                                               \
+        if (!(s)) return COSENU_ESTATE;                \
+    } while (0)
+
+#define HIPCHK(s, call)                                                                    \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            (s)->err = std::string(#call) + ": " + hipGetErrorString(e_);                  \
+            return e_ == hipErrorOutOfMemory ? COSENU_ENOMEM : COSENU_EDEVICE;             \
+        }                                                                                  \
+    } while (0)
+
+namespace {
+
+int sim_alloc(cosenu_sim *s, void **p, size_t bytes) {
+    HIPCHK(s, hipMalloc(p, bytes));
+    s->allocs.push_back(*p);
+    s->bytes += bytes;
+    return COSENU_OK;
+}
+
+void destroy_graphs(cosenu_sim *s) {
+    if (s->g1) (void)hipGraphExecDestroy(s->g1);
+    if (s->gN) (void)hipGraphExecDestroy(s->gN);
+    s->g1 = s->gN = nullptr;
+    s->graphs_ok = false;
+}
+
+int enqueue_stages(cosenu_sim *s, hipStream_t st, int nsteps) {
+    const int blocks = blocks_for(s->d);
+    for (int k = 0; k < nsteps; ++k)
+        for (int stage = 0; stage < 4; ++stage) HIPCHK(s, launch_stage(s->d, stage, blocks, st));
+    return COSENU_OK;
+}
+
+int capture(cosenu_sim *s, int nsteps, hipGraphExec_t *out) {
+    hipGraph_t graph = nullptr;
+    HIPCHK(s, hipStreamBeginCapture(s->own_stream, hipStreamCaptureModeRelaxed));
+    int rc = enqueue_stages(s, s->own_stream, nsteps);
+    hipError_t e = hipStreamEndCapture(s->own_stream, &graph);
+    if (rc != COSENU_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        s->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+        return COSENU_EDEVICE;
+    }
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        s->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+        return COSENU_EDEVICE;
+    }
+    return COSENU_OK;
+}
+
+int build_graphs(cosenu_sim *s) {
+    destroy_graphs(s);
+    int rc = capture(s, 1, &s->g1);
+    if (rc) return rc;
+    rc = capture(s, s->gN_steps, &s->gN);
+    if (rc) return rc;
+    s->graphs_ok = true;
+    return COSENU_OK;
+}
+
+int ensure_diag_capacity(cosenu_sim *s) {
+    if ((size_t)s->d.ntasks <= s->diag_cap) return COSENU_OK;
+    // the partial buffer is sized for the smallest segment length ever used
+    size_t need = (size_t)s->d.ntasks;
+    void *p = nullptr;
+    int rc = sim_alloc(s, &p, need * kDiagQ * sizeof(double));
+    if (rc) return rc;
+    s->diag_part = (double *)p;
+    s->diag_cap = need;
+    return COSENU_OK;
+}
+
+int compute_conserved(cosenu_sim *s, cosenu_conserved_t *out) {
+    int rc = ensure_diag_capacity(s);
+    if (rc) return rc;
+    HIPCHK(s, launch_diag(s->d, s->diag_part, blocks_for(s->d), s->stream));
+    std::vector<double> part((size_t)s->d.ntasks * kDiagQ);
+    HIPCHK(s, hipMemcpyAsync(part.data(), s->diag_part, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    finish_conserved(s->prm, s->d, part, s->ee0_nu, s->ee0_nubar, s->t, s->step, out);
+    return COSENU_OK;
+}
+
+int upload_state(cosenu_sim *s, const double *host) {
+    const size_t n = (size_t)8 * s->d.nz * s->d.nv;
+    HIPCHK(s, hipMemcpyAsync(s->d.y, host, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, launch_moments_init(s->d, blocks_for(s->d), s->stream));
+    cosenu_conserved_t c;
+    int rc = compute_conserved(s, &c);
+    if (rc) return rc;
+    s->ee0_nu = c.ee_nu;
+    s->ee0_nubar = c.ee_nubar;
+    return COSENU_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *cosenu_strerror(int code) { return strerror_code(code); }
+
+const char *cosenu_last_error(const cosenu_sim *s) { return s ? s->err.c_str() : "null handle"; }
+
+int cosenu_params_default(cosenu_params *p) {
+    if (!p) return COSENU_EINVAL;
+    std::memset(p, 0, sizeof *p);
+    p->nz = 512;
+    p->nv = 32;
+    p->scheme = COSENU_FD_KO;
+    p->precision = COSENU_FP64;
+    p->L = 400.0;
+    p->cfl = 0.4;
+    p->mu = 1.0;
+    p->omega = 0.0;
+    p->theta = 37.0 * 3.14159265358979323846 / 180.0;
+    p->lambda = 0.0;
+    p->alpha = 0.9;
+    p->sigma_nu = 0.6;
+    p->sigma_nubar = 0.5;
+    p->pert_amp = 1e-6;
+    p->pert_width = 50.0;
+    p->phase = 0.0;
+    p->ko_eps = 0.1;
+    p->weno_eps = 1e-6;
+    return COSENU_OK;
+}
+
+void cosenu_destroy(cosenu_sim *s) {
+    if (!s) return;
+    if (s->own_stream) (void)hipStreamSynchronize(s->own_stream);
+    if (s->stream && s->stream != s->own_stream) (void)hipStreamSynchronize(s->stream);
+    destroy_graphs(s);
+    for (void *p : s->allocs) (void)hipFree(p);
+    if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
+    delete s;
+}
+
+int cosenu_create(const cosenu_params *p, cosenu_sim **out) {
+    if (!p || !out) return COSENU_EINVAL;
+    *out = nullptr;
+    if (!validate_params(*p).empty()) return COSENU_EINVAL;
+    cosenu_sim *s = new (std::nothrow) cosenu_sim();
+    if (!s) return COSENU_ENOMEM;
+    s->prm = *p;
+    auto fail = [&](int rc) {
+        cosenu_destroy(s);
+        return rc;
+    };
+    if (hipGetDevice(&s->device) != hipSuccess) return fail(COSENU_EDEVICE);
+    if (hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking) != hipSuccess) return fail(COSENU_EDEVICE);
+    s->stream = s->own_stream;
+
+    fill_desc_constants(*p, s->d);
+    const int tuned = tuned_seg(p->scheme, p->precision, p->nz, p->nv);
+    if (tuned > 0) set_shape(s->d, tuned);
+
+    const int nz = p->nz, nv = p->nv;
+    const size_t cells = (size_t)nz * nv;
+    const size_t f64 = 8 * cells * sizeof(double);
+    const size_t ybbytes = 8 * cells * (p->precision == COSENU_FP64 ? sizeof(double) : sizeof(float));
+    void *ptr = nullptr;
+    int rc;
+    if ((rc = sim_alloc(s, &ptr, f64))) return fail(rc);
+    s->d.y = (double *)ptr;
+    if ((rc = sim_alloc(s, &ptr, f64))) return fail(rc);
+    s->d.acc = (double *)ptr;
+    if ((rc = sim_alloc(s, &ptr, f64))) return fail(rc);
+    s->d.ya = ptr;
+    if ((rc = sim_alloc(s, &ptr, ybbytes))) return fail(rc);
+    s->d.yb = ptr;
+    const size_t mom_bytes = (size_t)nz * s->d.vchunks * kMomQ * sizeof(double);
+    for (int k = 0; k < 4; ++k) {
+        if ((rc = sim_alloc(s, &ptr, mom_bytes))) return fail(rc);
+        s->d.mom[k] = (double *)ptr;
+    }
+    // per-bin constants
+    const std::vector<double> vel = bin_velocities(nv);
+    const std::vector<double> g = gaussian_distribution(nv, p->sigma_nu);
+    const std::vector<double> gb = gaussian_distribution(nv, p->sigma_nubar);
+    std::vector<double> agb(nv);
+    for (int j = 0; j < nv; ++j) agb[j] = p->alpha * gb[j];
+    double *consts = nullptr;
+    if ((rc = sim_alloc(s, (void **)&consts, 4 * nv * sizeof(double)))) return fail(rc);
+    std::vector<double> hostc(4 * (size_t)nv);
+    std::copy(vel.begin(), vel.end(), hostc.begin());
+    std::copy(g.begin(), g.end(), hostc.begin() + nv);
+    std::copy(gb.begin(), gb.end(), hostc.begin() + 2 * nv);
+    std::copy(agb.begin(), agb.end(), hostc.begin() + 3 * nv);
+    if (hipMemcpy(consts, hostc.data(), hostc.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(COSENU_EDEVICE);
+    s->d.vel = consts;
+    s->d.g = consts + nv;
+    s->d.gb = consts + 2 * nv;
+    s->d.agb = consts + 3 * nv;
+    // scratch buffers that never move (so captured graphs stay valid)
+    if ((rc = sim_alloc(s, &ptr, (size_t)nz * s->d.vchunks * 8 * sizeof(double)))) return fail(rc);
+    s->mom_out = (double *)ptr;
+    {
+        // diagnostics partials sized for the finest launch shape the tuner may pick (seg >= 1)
+        const size_t cap = (size_t)nz * s->d.vchunks;
+        if ((rc = sim_alloc(s, &ptr, cap * kDiagQ * sizeof(double)))) return fail(rc);
+        s->diag_part = (double *)ptr;
+        s->diag_cap = cap;
+    }
+    // initial data (eqs:perts)
+    std::vector<double> y0;
+    initial_state(*p, y0);
+    if ((rc = upload_state(s, y0.data()))) return fail(rc);
+    if ((rc = build_graphs(s))) return fail(rc);
+    *out = s;
+    return COSENU_OK;
+}
+
+int cosenu_step(cosenu_sim *s, int64_t nsteps) {
+    SIM_CHECK(s);
+    if (nsteps < 0) return COSENU_EINVAL;
+    if (nsteps == 0) return COSENU_OK;
+    if (!s->graphs_ok) {
+        int rc = build_graphs(s);
+        if (rc) return rc;
+    }
+    int64_t big = nsteps / s->gN_steps, rem = nsteps % s->gN_steps;
+    for (int64_t k = 0; k < big; ++k) HIPCHK(s, hipGraphLaunch(s->gN, s->stream));
+    for (int64_t k = 0; k < rem; ++k) HIPCHK(s, hipGraphLaunch(s->g1, s->stream));
+    s->step += nsteps;
+    s->t += (double)nsteps * s->d.dt;
+    return COSENU_OK;
+}
+
+int cosenu_sync(cosenu_sim *s) {
+    SIM_CHECK(s);
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return COSENU_OK;
+}
+
+int cosenu_get_state(cosenu_sim *s, double *out, size_t n) {
+    SIM_CHECK(s);
+    const size_t need = (size_t)8 * s->d.nz * s->d.nv;
+    if (!out || n < need) return COSENU_EINVAL;
+    HIPCHK(s, hipMemcpyAsync(out, s->d.y, need * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return COSENU_OK;
+}
+
+int cosenu_set_state(cosenu_sim *s, const double *in, size_t n) {
+    SIM_CHECK(s);
+    const size_t need = (size_t)8 * s->d.nz * s->d.nv;
+    if (!in || n < need) return COSENU_EINVAL;
+    return upload_state(s, in);
+}
+
+int cosenu_set_clock(cosenu_sim *s, double t, int64_t step) {
+    SIM_CHECK(s);
+    if (!std::isfinite(t) || step < 0) return COSENU_EINVAL;
+    s->t = t;
+    s->step = step;
+    return COSENU_OK;
+}
+
+int cosenu_moments(cosenu_sim *s, double *out, size_t n) {
+    SIM_CHECK(s);
+    const int nz = s->d.nz, vch = s->d.vchunks;
+    if (!out || n < (size_t)8 * nz) return COSENU_EINVAL;
+    HIPCHK(s, launch_moments_out(s->d, s->mom_out, blocks_for(s->d), s->stream));
+    std::vector<double> part((size_t)nz * vch * 8);
+    HIPCHK(s, hipMemcpyAsync(part.data(), s->mom_out, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (int z = 0; z < nz; ++z) {
+        for (int q = 0; q < 8; ++q) {
+            double acc = 0.0;
+            for (int c = 0; c < vch; ++c) acc += part[((size_t)z * vch + c) * 8 + q];
+            // part holds (D_ee, D_xx, ReD, ImD, v D_ee, ...); out is [z][m][q]
+            out[(size_t)z * 8 + q] = s->d.dv * acc;
+        }
+    }
+    return COSENU_OK;
+}
+
+int cosenu_conserved(cosenu_sim *s, cosenu_conserved_t *out) {
+    SIM_CHECK(s);
+    if (!out) return COSENU_EINVAL;
+    int rc = compute_conserved(s, out);
+    if (rc) return rc;
+    return out->nonfinite ? COSENU_ENONFINITE : COSENU_OK;
+}
+
+int cosenu_info(cosenu_sim *s, cosenu_info_t *out) {
+    SIM_CHECK(s);
+    if (!out) return COSENU_EINVAL;
+    std::memset(out, 0, sizeof *out);
+    out->dt = s->d.dt;
+    out->dz = s->prm.L / s->prm.nz;
+    out->dv = s->d.dv;
+    out->t = s->t;
+    out->step = s->step;
+    out->device_bytes = s->bytes;
+    out->seg_rows = s->d.seg;
+    out->lanes_per_row = 1 << s->d.lr_log2;
+    out->v_chunks = s->d.vchunks;
+    out->blocks_per_stage = blocks_for(s->d);
+    out->bytes_per_step = bytes_per_cell_step(s->prm.precision) * (double)s->d.nz * s->d.nv;
+    return COSENU_OK;
+}
+
+int cosenu_set_stream(cosenu_sim *s, void *hip_stream) {
+    SIM_CHECK(s);
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->stream = hip_stream ? (hipStream_t)hip_stream : s->own_stream;
+    return COSENU_OK;
+}
+
+int cosenu_set_seg_rows(cosenu_sim *s, int32_t seg_rows) {
+    SIM_CHECK(s);
+    if (seg_rows < 0) return COSENU_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    int seg = seg_rows;
+    if (seg == 0) {
+        seg = tuned_seg(s->prm.scheme, s->prm.precision, s->prm.nz, s->prm.nv);
+        if (seg == 0) seg = default_seg_rows(s->prm.nz, s->prm.nv);
+    }
+    set_shape(s->d, seg);
+    return build_graphs(s);
+}
+
+int cosenu_time_steps(cosenu_sim *s, int64_t nsteps, double *ms) {
+    SIM_CHECK(s);
+    if (!ms || nsteps < 0) return COSENU_EINVAL;
+    hipEvent_t a, b;
+    HIPCHK(s, hipEventCreate(&a));
+    HIPCHK(s, hipEventCreate(&b));
+    int rc = COSENU_OK;
+    if (hipEventRecord(a, s->stream) != hipSuccess) rc = COSENU_EDEVICE;
+    if (!rc) rc = cosenu_step(s, nsteps);
+    if (!rc && hipEventRecord(b, s->stream) != hipSuccess) rc = COSENU_EDEVICE;
+    if (!rc && hipEventSynchronize(b) != hipSuccess) rc = COSENU_EDEVICE;
+    float f = 0.f;
+    if (!rc && hipEventElapsedTime(&f, a, b) != hipSuccess) rc = COSENU_EDEVICE;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = f;
+    if (rc == COSENU_EDEVICE && s->err.empty()) s->err = "event timing failed";
+    return rc;
+}
+
+int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage) {
+    SIM_CHECK(s);
+    if (!ms_stage || nsteps < 0) return COSENU_EINVAL;
+    std::vector<hipEvent_t> ev(8);
+    for (auto &e : ev) HIPCHK(s, hipEventCreate(&e));
+    for (int k = 0; k < 4; ++k) ms_stage[k] = 0.0;
+    const int blocks = blocks_for(s->d);
+    int rc = COSENU_OK;
+    for (int64_t n = 0; n < nsteps && !rc; ++n) {
+        for (int stage = 0; stage < 4; ++stage) {
+            if (hipEventRecord(ev[2 * stage], s->stream) != hipSuccess) rc = COSENU_EDEVICE;
+            if (!rc && launch_stage(s->d, stage, blocks, s->stream) != hipSuccess) rc = COSENU_EDEVICE;
+            if (!rc && hipEventRecord(ev[2 * stage + 1], s->stream) != hipSuccess) rc = COSENU_EDEVICE;
+        }
+        if (!rc && hipEventSynchronize(ev[7]) != hipSuccess) rc = COSENU_EDEVICE;
+        for (int stage = 0; stage < 4 && !rc; ++stage) {
+            float f = 0.f;
+            if (hipEventElapsedTime(&f, ev[2 * stage], ev[2 * stage + 1]) != hipSuccess) rc = COSENU_EDEVICE;
+            ms_stage[stage] += f;
+        }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (!rc) {
+        s->step += nsteps;
+        s->t += (double)nsteps * s->d.dt;
+    } else if (s->err.empty()) {
+        s->err = "stage timing failed";
+    }
+    return rc;
+}
+
+int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
+    SIM_CHECK(s);
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    // Stages 1..3 write only scratch (Y2, Y3, Y4, acc and the moments of
+    // those stage values), so timing them leaves the state untouched.
+    const int cands[] = {4, 8, 16, 32, 64, 128, 256};
+    const InstDesc keep = s->d;
+    int best = keep.seg;
+    double best_ms = 1e300;
+    hipEvent_t a, b;
+    HIPCHK(s, hipEventCreate(&a));
+    HIPCHK(s, hipEventCreate(&b));
+    for (int c : cands) {
+        if (c > s->d.nz) break;
+        set_shape(s->d, c);
+        const int blocks = blocks_for(s->d);
+        double total = 0.0;
+        bool ok = true;
+        for (int rep = 0; rep < 4 && ok; ++rep) {
+            ok = hipEventRecord(a, s->stream) == hipSuccess;
+            for (int stage = 0; stage < 3 && ok; ++stage) ok = launch_stage(s->d, stage, blocks, s->stream) == hipSuccess;
+            ok = ok && hipEventRecord(b, s->stream) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+            float f = 0.f;
+            ok = ok && hipEventElapsedTime(&f, a, b) == hipSuccess;
+            if (rep > 0) total += f;  // first repetition warms up
+        }
+        if (!ok) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            s->d = keep;
+            s->err = "autotune launch failed";
+            return COSENU_EDEVICE;
+        }
+        if (total < best_ms) {
+            best_ms = total;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    s->d = keep;
+    set_shape(s->d, best);
+    store_tuned_seg(s->prm.scheme, s->prm.precision, s->prm.nz, s->prm.nv, best);
+    if (seg_rows) *seg_rows = best;
+    return build_graphs(s);
+}
+
+}  // extern "C"

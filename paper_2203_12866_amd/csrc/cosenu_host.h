@@ -1,0 +1,28 @@
+// Host-side helpers shared by the single-instance and batched runtimes.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "cosenu.h"
+#include "cosenu_internal.h"
+
+namespace cosenu {
+
+const char *strerror_code(int code);
+std::string validate_params(const cosenu_params &p);
+std::vector<double> bin_velocities(int nv);
+std::vector<double> gaussian_distribution(int nv, double sigma);
+double time_step(const cosenu_params &p);
+void initial_state(const cosenu_params &p, std::vector<double> &y);
+int lr_log2_for(int nv);
+int default_seg_rows(int nz, int nv);
+void set_shape(InstDesc &d, int seg);
+double bytes_per_cell_step(int form);
+void fill_desc_constants(const cosenu_params &p, InstDesc &d);
+void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vector<double> &part, double ee0n,
+                      double ee0b, double t, int64_t step, cosenu_conserved_t *out);
+int tuned_seg(int scheme, int form, int nz, int nv);
+void store_tuned_seg(int scheme, int form, int nz, int nv, int seg);
+
+}  // namespace cosenu

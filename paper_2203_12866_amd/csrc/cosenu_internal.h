@@ -1,0 +1,73 @@
+// Internal interface between the host runtime and the gfx950 kernels.
+// Not part of the public ABI (see include/cosenu.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cosenu {
+
+constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kWavesPerBlock = 4;   // stage kernels run 256-thread workgroups
+constexpr int kMomQ = 6;            // reduced quantities per row and part:
+                                    //   sum D3, sum ReDex, sum ImDex, and the same times v
+constexpr int kDiagQ = 12;          // per-task partials of the conserved-quantity kernel
+
+// Everything one stage launch needs about one simulation.  Passed by value to
+// the single-instance kernels and stored in device memory for the batch.
+struct InstDesc {
+    int32_t nz, nv;
+    int32_t scheme, form;
+    int32_t lr_log2;   // lanes per row group = 1 << lr_log2 (<= 64)
+    int32_t vchunks;   // 64-bin chunks per row (1 when nv <= 64); = moment parts per row
+    int32_t seg;       // rows per lane group
+    int32_t nseg;      // ceil(nz / seg)
+    int32_t ntasks;    // nseg * vchunks
+    int32_t pad_;
+    double dz_inv;     // 1 / dz
+    double dt;
+    double mudv;       // mu * dv
+    double h3vac;      // (H_vac)_ee - (H_vac)_xx = -omega cos 2theta
+    double hexvac;     // (H_vac)_ex = omega/2 sin 2theta
+    double lam;        // matter potential
+    double ko16;       // ko_eps / 16
+    double weno_eps;
+    double dv;
+    const double *g;   // g_nu per bin                       [nv]
+    const double *gb;  // g_nubar per bin                    [nv]
+    const double *agb; // alpha * g_nubar per bin            [nv]
+    const double *vel; // bin midpoints                      [nv]
+    double *y;         // state, FP64                        [8][nz][nv]
+    double *acc;       // RK4 accumulator, FP64              [8][nz][nv]
+    void *ya;          // Y2 / Y4 stage values, FP64         [8][nz][nv]
+    void *yb;          // Y3 stage values, FP64 or FP32      [8][nz][nv]
+    double *mom[4];    // row moment partials of the stage inputs y, Y2, Y3, Y4
+                       //   [nz][vchunks][kMomQ]
+};
+
+// One wave's work item in a batched launch: instance and first task.
+struct WaveTask {
+    int32_t inst;
+    int32_t task0;
+};
+
+// ---- launchers (stage_kernels.hip) -----------------------------------------
+hipError_t launch_stage(const InstDesc &d, int stage, int blocks, hipStream_t st);
+hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st);
+hipError_t launch_batch_stage(const InstDesc *d_descs, const WaveTask *d_tasks, int nwaves, int scheme, int form,
+                              int stage, int blocks, hipStream_t st);
+// ---- diagnostics (diag_kernels.hip) ----------------------------------------
+// per task partials [ntasks][kDiagQ]:
+//   0..3 M0 (trace, x, y, z) summed g P - alpha gbar Pbar~ (without dz dv)
+//   4 N_nu, 5 N_nubar (sum g Tr rho, sum gbar Tr rhobar), 6 sum g |dP_nu|, 7 sum g,
+//   8 sum g rho_ee, 9 sum gbar rhobar_ee, 10 max |dP| over both species, 11 non-finite count
+hipError_t launch_diag(const InstDesc &d, double *partials, int blocks, hipStream_t st);
+// per row and chunk [nz][vchunks][8]: dv sum D_q and dv sum v D_q, q = ee, xx, Re ex, Im ex
+hipError_t launch_moments_out(const InstDesc &d, double *out, int blocks, hipStream_t st);
+
+// number of workgroups covering all tasks of one instance
+int blocks_for(const InstDesc &d);
+int groups_per_wave(const InstDesc &d);
+
+}  // namespace cosenu

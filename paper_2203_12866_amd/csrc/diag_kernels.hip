@@ -1,0 +1,132 @@
+// Off-path reductions over the state (FP64, fixed summation order):
+// conserved quantities and error measures of Sec. 5, and the per-row angular
+// moments of D = g rho - alpha gbar rhobar^*.  Same task decomposition as the
+// stage kernels (row groups of lanes over v, segments of rows over z); each
+// lane accumulates its bin down the segment, then the group reduces with an
+// xor butterfly and lane 0 writes one partial per task.
+#include "cosenu_internal.h"
+
+namespace cosenu {
+namespace {
+
+__device__ __forceinline__ double group_sum(double x, int lr_log2) {
+    for (int off = (1 << lr_log2) >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return x;
+}
+__device__ __forceinline__ double group_max(double x, int lr_log2) {
+    for (int off = (1 << lr_log2) >> 1; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, kWave));
+    return x;
+}
+
+__global__ __launch_bounds__(kWave *kWavesPerBlock) void diag_kernel(InstDesc d, double *partials) {
+    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int G = kWave >> d.lr_log2;
+    const int task = wave * G + (lane >> d.lr_log2);
+    if (wave * G >= d.ntasks) return;
+    const int l = lane & ((1 << d.lr_log2) - 1);
+    const bool task_ok = task < d.ntasks;
+    const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
+    const int vc = task_ok ? task % vchunks : 0;
+    const int segi = task_ok ? task / vchunks : 0;
+    const int j = vc * kWave + l;
+    const bool lane_on = task_ok && j < nv;
+    const int jl = j < nv ? j : nv - 1;
+    const int z0 = segi * d.seg;
+    const int z1 = task_ok ? min(nz, z0 + d.seg) : z0;
+    const double g = d.g[jl], gb = d.gb[jl], ag = d.agb[jl];
+    const size_t plane = (size_t)nz * nv;
+    double a[kDiagQ];
+#pragma unroll
+    for (int q = 0; q < kDiagQ; ++q) a[q] = 0.0;
+    if (lane_on) {
+        for (int i = z0; i < z1; ++i) {
+            const size_t at = (size_t)i * nv + jl;
+            double o[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                o[c] = d.y[c * plane + at];
+                if (!isfinite(o[c])) a[11] += 1.0;
+            }
+            // polarisation vectors: rho = (P0 + P.sigma)/2; Pbar~ belongs to rhobar^*
+            const double P0 = o[0] + o[1], P1 = 2.0 * o[2], P2 = -2.0 * o[3], P3 = o[0] - o[1];
+            const double Q0 = o[4] + o[5], Q1 = 2.0 * o[6], Q2 = 2.0 * o[7], Q3 = o[4] - o[5];
+            a[0] += g * P0 - ag * Q0;
+            a[1] += g * P1 - ag * Q1;
+            a[2] += g * P2 - ag * Q2;
+            a[3] += g * P3 - ag * Q3;
+            a[4] += g * P0;
+            a[5] += gb * Q0;
+            const double dpn = fabs(sqrt(P1 * P1 + P2 * P2 + P3 * P3) - 1.0);
+            const double dpb = fabs(sqrt(Q1 * Q1 + Q2 * Q2 + Q3 * Q3) - 1.0);
+            a[6] += g * dpn;
+            a[7] += g;
+            a[8] += g * o[0];
+            a[9] += gb * o[4];
+            a[10] = fmax(a[10], fmax(dpn, dpb));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kDiagQ; ++q) a[q] = (q == 10) ? group_max(a[q], d.lr_log2) : group_sum(a[q], d.lr_log2);
+    if (task_ok && l == 0) {
+#pragma unroll
+        for (int q = 0; q < kDiagQ; ++q) partials[(size_t)task * kDiagQ + q] = a[q];
+    }
+}
+
+__global__ __launch_bounds__(kWave *kWavesPerBlock) void moments_out_kernel(InstDesc d, double *out) {
+    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int G = kWave >> d.lr_log2;
+    const int task = wave * G + (lane >> d.lr_log2);
+    if (wave * G >= d.ntasks) return;
+    const int l = lane & ((1 << d.lr_log2) - 1);
+    const bool task_ok = task < d.ntasks;
+    const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
+    const int vc = task_ok ? task % vchunks : 0;
+    const int segi = task_ok ? task / vchunks : 0;
+    const int j = vc * kWave + l;
+    const bool lane_on = task_ok && j < nv;
+    const int jl = j < nv ? j : nv - 1;
+    const int z0 = segi * d.seg;
+    const int z1 = task_ok ? min(nz, z0 + d.seg) : z0;
+    const double g = d.g[jl], ag = d.agb[jl], v = d.vel[jl];
+    const size_t plane = (size_t)nz * nv;
+    for (int i = z0; i < z0 + d.seg; ++i) {
+        const bool row_in = i < z1;
+        const int irow = min(i, nz - 1);
+        const size_t at = (size_t)irow * nv + jl;
+        double m[8];
+        if (row_in && lane_on) {
+            const double Dee = g * d.y[0 * plane + at] - ag * d.y[4 * plane + at];
+            const double Dxx = g * d.y[1 * plane + at] - ag * d.y[5 * plane + at];
+            const double Dre = g * d.y[2 * plane + at] - ag * d.y[6 * plane + at];
+            const double Dim = g * d.y[3 * plane + at] + ag * d.y[7 * plane + at];
+            m[0] = Dee; m[1] = Dxx; m[2] = Dre; m[3] = Dim;
+            m[4] = v * Dee; m[5] = v * Dxx; m[6] = v * Dre; m[7] = v * Dim;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) m[q] = 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) m[q] = group_sum(m[q], d.lr_log2);
+        if (row_in && l == 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) out[((size_t)irow * vchunks + vc) * 8 + q] = m[q];
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_diag(const InstDesc &d, double *partials, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(diag_kernel, dim3(blocks), dim3(kWave * kWavesPerBlock), 0, st, d, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_out(const InstDesc &d, double *out, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(moments_out_kernel, dim3(blocks), dim3(kWave * kWavesPerBlock), 0, st, d, out);
+    return hipGetLastError();
+}
+
+}  // namespace cosenu

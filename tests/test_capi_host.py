@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI library that need no GPU: it loads, exports
+every function include/cosenu.h declares, and rejects invalid parameters
+before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2203_12866_amd import cosenu
+from paper_2203_12866_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cosenu.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cosenu_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = cosenu.lib()
+    names = declared_functions()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_default_params_are_the_fiducial_case():
+    p = cosenu.default_params()
+    assert (p.nz, p.nv, p.scheme, p.precision) == (512, 32, 0, 0)
+    assert (p.L, p.cfl, p.mu, p.alpha, p.sigma_nu, p.sigma_nubar) == (400.0, 0.4, 1.0, 0.9, 0.6, 0.5)
+    assert (p.ko_eps, p.weno_eps, p.pert_amp, p.pert_width) == (0.1, 1e-6, 1e-6, 50.0)
+    assert abs(p.theta - 37.0 * 3.141592653589793 / 180.0) < 1e-15
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nz", 4), ("nv", 1), ("nv", 0), ("L", 0.0), ("L", float("nan")), ("cfl", 0.0), ("cfl", 2.5),
+    ("sigma_nu", 0.0), ("alpha", -0.1), ("pert_amp", 1.5), ("pert_width", 0.0), ("weno_eps", 0.0),
+    ("ko_eps", -1.0), ("scheme", 2), ("precision", 7), ("mu", float("inf")),
+])
+def test_invalid_parameters_rejected_before_device(field, value):
+    p = cosenu.default_params()
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    assert cosenu.lib().cosenu_create(ctypes.byref(p), ctypes.byref(h)) == cosenu.EINVAL
+    assert not h.value
+
+
+def test_weno_needs_nine_rows():
+    p = cosenu.default_params()
+    p.scheme, p.nz = cosenu.FV_WENO7, 8
+    h = ctypes.c_void_p()
+    assert cosenu.lib().cosenu_create(ctypes.byref(p), ctypes.byref(h)) == cosenu.EINVAL
+
+
+def test_null_handles_and_errors():
+    L = cosenu.lib()
+    assert L.cosenu_step(None, 1) == cosenu.ESTATE
+    assert L.cosenu_sync(None) == cosenu.ESTATE
+    assert L.cosenu_batch_step(None, 1) == cosenu.ESTATE
+    assert L.cosenu_params_default(None) == cosenu.EINVAL
+    assert L.cosenu_batch_create(None, 0, None) == cosenu.EINVAL
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.cosenu_strerror(code)
+    L.cosenu_destroy(None)
+    L.cosenu_batch_destroy(None)
+
+
+def test_batch_rejects_one_bad_instance():
+    good = cosenu.default_params()
+    bad = cosenu.default_params()
+    bad.nv = 1
+    arr = (cosenu.Params * 2)(good, bad)
+    h = ctypes.c_void_p()
+    assert cosenu.lib().cosenu_batch_create(arr, 2, ctypes.byref(h)) == cosenu.EINVAL
+
+
+def test_workloads_are_seeded_and_in_range():
+    assert wl.small_fd(3) == wl.small_fd(3)
+    assert wl.fd_16384x128(2)["alpha"] != wl.fd_16384x128(5)["alpha"]
+    w = wl.fd_16384x128(2)
+    assert 0.8 <= w["alpha"] <= 1.0 and (w["nz"], w["nv"], w["L"], w["steps"]) == (16384, 128, 1600.0, 2000)
+    b = wl.batch_64(4)
+    assert len(b) == 64
+    for w in b:
+        assert 2048 <= w["nz"] <= 32768 and w["nv"] in (32, 64, 128, 256)
+        assert abs(w["L"] / w["nz"] - 0.09765625) < 1e-12
+    p = cosenu.params_from(wl.fv_65536x256(3))
+    assert (p.nz, p.nv, p.scheme, p.omega) == (65536, 256, 1, 1e-3)

@@ -1,0 +1,109 @@
+"""Systems properties of the HIP path: bitwise determinism, checkpoint and
+resume through get_state/set_state, batched instances equal to the same
+instances run alone, stream binding, and detection of a blown-up state."""
+import numpy as np
+import pytest
+
+from paper_2203_12866_amd import cosenu
+from paper_2203_12866_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def test_run_twice_bitwise():
+    for scheme in (wl.FD_KO, wl.FV_WENO7):
+        w = wl.small_fd(5)
+        w.update(scheme=scheme)
+        outs = []
+        for _ in range(2):
+            with cosenu.Sim(w) as s:
+                s.step(37)
+                outs.append(s.get_state())
+        assert np.array_equal(outs[0], outs[1])
+
+
+def test_checkpoint_resume_bitwise():
+    for prec in (wl.FP64, wl.FP32_ACC64):
+        w = wl.small_fv(6)
+        w.update(precision=prec, omega=0.1)
+        with cosenu.Sim(w) as a:
+            a.step(20)
+            full = a.get_state()
+            ca = a.conserved()
+        with cosenu.Sim(w) as b:
+            b.step(10)
+            ck = b.get_state()
+            t, step = b.info()["t"], b.info()["step"]
+        with cosenu.Sim(w) as c:
+            c.set_state(ck)
+            c.set_clock(t, step)
+            c.step(10)
+            assert np.array_equal(c.get_state(), full)
+            assert c.info()["step"] == 20
+
+
+def test_get_set_roundtrip_and_clock():
+    w = wl.small_fd(1)
+    y = wl.random_state(512, 32, seed=3)
+    with cosenu.Sim(w) as s:
+        s.set_state(y)
+        assert np.array_equal(s.get_state(), y)
+        s.step(4)
+        info = s.info()
+        assert info["step"] == 4 and abs(info["t"] - 4 * info["dt"]) < 1e-12
+        assert s.conserved()["Pee_nu"] != 0.0
+
+
+def test_batch_instances_equal_solo_runs():
+    ws = []
+    for i, (scheme, nz, nv) in enumerate([(0, 300, 32), (1, 257, 64), (0, 190, 100), (1, 64, 16), (0, 1000, 8)]):
+        w = wl.small_fd(10 + i)
+        w.update(nz=nz, nv=nv, L=0.5 * nz, scheme=scheme, omega=0.05 * i, lam=0.2 * i, alpha=0.8 + 0.03 * i)
+        ws.append(w)
+    for prec in (wl.FP64, wl.FP32_ACC64):
+        for w in ws:
+            w["precision"] = prec
+        b = cosenu.Batch(ws)
+        b.step(9)
+        for i, w in enumerate(ws):
+            with cosenu.Sim(w) as s:
+                s.step(9)
+                solo = s.get_state()
+            assert np.array_equal(b.get_state(i), solo), (prec, i)
+            assert b.info(i)["step"] == 9
+        c = b.conserved(3)
+        assert c["nonfinite"] == 0
+        b.close()
+
+
+def test_torch_stream_binding():
+    import torch
+    w = wl.small_fd(2)
+    with cosenu.Sim(w) as s:
+        ref_state = None
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            s.bind_torch_stream()
+            s.step(5)
+        torch.cuda.synchronize()
+        s.set_stream(None)
+        got = s.get_state()
+    with cosenu.Sim(w) as s2:
+        s2.step(5)
+        ref_state = s2.get_state()
+    assert np.array_equal(got, ref_state)
+
+
+def test_blow_up_is_reported_as_nonfinite():
+    """A state with huge values under the FD scheme at cfl = 2 overflows; the
+    diagnostics call reports it."""
+    w = wl.small_fd(1)
+    w.update(nz=64, nv=8, L=10.0, cfl=2.0, ko_eps=0.0)
+    y = wl.random_state(64, 8, seed=1, scale=1e150)
+    with cosenu.Sim(w) as s:
+        s.set_state(y)
+        s.step(50)
+        with pytest.raises(cosenu.CosenuError) as e:
+            s.conserved()
+        assert e.value.code == cosenu.ENONFINITE
+        assert s.conserved(allow_nonfinite=True)["nonfinite"] > 0
