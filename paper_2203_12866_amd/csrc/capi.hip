@@ -42,7 +42,7 @@ std::string validate_params(const cosenu_params &p) {
         return buf;
     }
     if (p.nv < 2) return "nv must be >= 2 (with one bin max|v| = 0 and dt is undefined)";
-    if ((double)p.nz * (double)p.nv > 4.0e9) return "nz * nv too large";
+    if ((double)p.nz * (double)p.nv > (double)(1u << 29)) return "nz * nv above 2^29 cells (32-bit byte offsets per plane)";
     if (!(fin(p.L) && p.L > 0)) return "L must be finite and > 0";
     if (!(fin(p.cfl) && p.cfl > 0 && p.cfl <= 2.0)) return "cfl must be in (0, 2]";
     if (!(fin(p.mu) && fin(p.omega) && fin(p.theta) && fin(p.lambda))) return "mu, omega, theta, lambda must be finite";
@@ -113,8 +113,8 @@ int default_seg_rows(int nz, int nv) {
     const int lg = lr_log2_for(nv);
     const int G = kWave >> lg;
     const int vch = nv > kWave ? (nv + kWave - 1) / kWave : 1;
-    // aim at ~2048 waves per stage launch, segments of 4 .. 64 rows
-    long long target = (long long)nz * vch / ((long long)G * 2048);
+    // aim at ~2048 waves per stage launch (two species per row group), segments of 4 .. 64 rows
+    long long target = 2LL * nz * vch / ((long long)G * 2048);
     int s = 4;
     while (s * 2 <= target && s < 64) s *= 2;
     return s;
@@ -123,7 +123,10 @@ int default_seg_rows(int nz, int nv) {
 void set_shape(InstDesc &d, int seg) {
     d.seg = std::max(1, std::min(seg, d.nz));
     d.nseg = (d.nz + d.seg - 1) / d.seg;
-    d.ntasks = d.nseg * d.vchunks;
+    d.nrowtasks = d.nseg * d.vchunks;
+    const int G = kWave >> d.lr_log2;
+    d.tps = (d.nrowtasks + G - 1) / G * G;
+    d.ntasks = 2 * d.tps;
 }
 
 double bytes_per_cell_step(int form) {
@@ -155,7 +158,7 @@ void fill_desc_constants(const cosenu_params &p, InstDesc &d) {
 void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vector<double> &part, double ee0n,
                       double ee0b, double t, int64_t step, cosenu_conserved_t *out) {
     double a[kDiagQ] = {0};
-    for (int task = 0; task < d.ntasks; ++task) {
+    for (int task = 0; task < d.nrowtasks; ++task) {
         const double *q = &part[(size_t)task * kDiagQ];
         for (int k = 0; k < kDiagQ; ++k) {
             if (k == 10) a[k] = std::max(a[k], q[k]);
@@ -291,9 +294,9 @@ int build_graphs(cosenu_sim *s) {
 }
 
 int ensure_diag_capacity(cosenu_sim *s) {
-    if ((size_t)s->d.ntasks <= s->diag_cap) return COSENU_OK;
+    if ((size_t)s->d.nrowtasks <= s->diag_cap) return COSENU_OK;
     // the partial buffer is sized for the smallest segment length ever used
-    size_t need = (size_t)s->d.ntasks;
+    size_t need = (size_t)s->d.nrowtasks;
     void *p = nullptr;
     int rc = sim_alloc(s, &p, need * kDiagQ * sizeof(double));
     if (rc) return rc;
@@ -305,8 +308,8 @@ int ensure_diag_capacity(cosenu_sim *s) {
 int compute_conserved(cosenu_sim *s, cosenu_conserved_t *out) {
     int rc = ensure_diag_capacity(s);
     if (rc) return rc;
-    HIPCHK(s, launch_diag(s->d, s->diag_part, blocks_for(s->d), s->stream));
-    std::vector<double> part((size_t)s->d.ntasks * kDiagQ);
+    HIPCHK(s, launch_diag(s->d, s->diag_part, row_blocks_for(s->d), s->stream));
+    std::vector<double> part((size_t)s->d.nrowtasks * kDiagQ);
     HIPCHK(s, hipMemcpyAsync(part.data(), s->diag_part, part.size() * sizeof(double), hipMemcpyDeviceToHost,
                              s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -402,7 +405,7 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) {
     s->d.ya = ptr;
     if ((rc = sim_alloc(s, &ptr, ybbytes))) return fail(rc);
     s->d.yb = ptr;
-    const size_t mom_bytes = (size_t)nz * s->d.vchunks * kMomQ * sizeof(double);
+    const size_t mom_bytes = (size_t)nz * s->d.vchunks * 2 * kMomQ * sizeof(double);
     for (int k = 0; k < 4; ++k) {
         if ((rc = sim_alloc(s, &ptr, mom_bytes))) return fail(rc);
         s->d.mom[k] = (double *)ptr;
@@ -495,7 +498,7 @@ int cosenu_moments(cosenu_sim *s, double *out, size_t n) {
     SIM_CHECK(s);
     const int nz = s->d.nz, vch = s->d.vchunks;
     if (!out || n < (size_t)8 * nz) return COSENU_EINVAL;
-    HIPCHK(s, launch_moments_out(s->d, s->mom_out, blocks_for(s->d), s->stream));
+    HIPCHK(s, launch_moments_out(s->d, s->mom_out, row_blocks_for(s->d), s->stream));
     std::vector<double> part((size_t)nz * vch * 8);
     HIPCHK(s, hipMemcpyAsync(part.data(), s->mom_out, part.size() * sizeof(double), hipMemcpyDeviceToHost,
                              s->stream));

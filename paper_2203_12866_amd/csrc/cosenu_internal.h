@@ -12,7 +12,8 @@ constexpr int kWave = 64;           // CDNA wavefront width
 constexpr int kWavesPerBlock = 4;   // stage kernels run 256-thread workgroups
 constexpr int kMomQ = 6;            // reduced quantities per row and part:
                                     //   sum D3, sum ReDex, sum ImDex, and the same times v
-constexpr int kDiagQ = 12;          // per-task partials of the conserved-quantity kernel
+constexpr int kDiagQ = 12;
+constexpr int kChunkRows[2] = {4, 2};  // rows per load chunk of the stage kernels: FD, WENO7          // per-task partials of the conserved-quantity kernel
 
 // Everything one stage launch needs about one simulation.  Passed by value to
 // the single-instance kernels and stored in device memory for the batch.
@@ -23,8 +24,9 @@ struct InstDesc {
     int32_t vchunks;   // 64-bin chunks per row (1 when nv <= 64); = moment parts per row
     int32_t seg;       // rows per lane group
     int32_t nseg;      // ceil(nz / seg)
-    int32_t ntasks;    // nseg * vchunks
-    int32_t pad_;
+    int32_t nrowtasks; // nseg * vchunks: (segment, chunk) pairs
+    int32_t tps;       // stage tasks per species: nrowtasks padded to a multiple of the groups per wave
+    int32_t ntasks;    // stage tasks: 2 * tps (neutrinos, then antineutrinos)
     double dz_inv;     // 1 / dz
     double dt;
     double mudv;       // mu * dv
@@ -43,7 +45,7 @@ struct InstDesc {
     void *ya;          // Y2 / Y4 stage values, FP64         [8][nz][nv]
     void *yb;          // Y3 stage values, FP64 or FP32      [8][nz][nv]
     double *mom[4];    // row moment partials of the stage inputs y, Y2, Y3, Y4
-                       //   [nz][vchunks][kMomQ]
+                       //   [nz][vchunks][2 species][kMomQ]
 };
 
 // One wave's work item in a batched launch: instance and first task.
@@ -58,7 +60,7 @@ hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st);
 hipError_t launch_batch_stage(const InstDesc *d_descs, const WaveTask *d_tasks, int nwaves, int scheme, int form,
                               int stage, int blocks, hipStream_t st);
 // ---- diagnostics (diag_kernels.hip) ----------------------------------------
-// per task partials [ntasks][kDiagQ]:
+// per (segment, chunk) partials [nrowtasks][kDiagQ]:
 //   0..3 M0 (trace, x, y, z) summed g P - alpha gbar Pbar~ (without dz dv)
 //   4 N_nu, 5 N_nubar (sum g Tr rho, sum gbar Tr rhobar), 6 sum g |dP_nu|, 7 sum g,
 //   8 sum g rho_ee, 9 sum gbar rhobar_ee, 10 max |dP| over both species, 11 non-finite count
@@ -66,8 +68,9 @@ hipError_t launch_diag(const InstDesc &d, double *partials, int blocks, hipStrea
 // per row and chunk [nz][vchunks][8]: dv sum D_q and dv sum v D_q, q = ee, xx, Re ex, Im ex
 hipError_t launch_moments_out(const InstDesc &d, double *out, int blocks, hipStream_t st);
 
-// number of workgroups covering all tasks of one instance
+// number of workgroups covering all stage tasks / all (segment, chunk) tasks
 int blocks_for(const InstDesc &d);
+int row_blocks_for(const InstDesc &d);
 int groups_per_wave(const InstDesc &d);
 
 }  // namespace cosenu

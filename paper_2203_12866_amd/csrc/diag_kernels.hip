@@ -19,13 +19,13 @@ __device__ __forceinline__ double group_max(double x, int lr_log2) {
 }
 
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void diag_kernel(InstDesc d, double *partials) {
-    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & (kWave - 1);
     const int G = kWave >> d.lr_log2;
     const int task = wave * G + (lane >> d.lr_log2);
-    if (wave * G >= d.ntasks) return;
+    if (wave * G >= d.nrowtasks) return;
     const int l = lane & ((1 << d.lr_log2) - 1);
-    const bool task_ok = task < d.ntasks;
+    const bool task_ok = task < d.nrowtasks;
     const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
     const int vc = task_ok ? task % vchunks : 0;
     const int segi = task_ok ? task / vchunks : 0;
@@ -75,13 +75,13 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void diag_kernel(InstDesc d,
 }
 
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void moments_out_kernel(InstDesc d, double *out) {
-    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & (kWave - 1);
     const int G = kWave >> d.lr_log2;
     const int task = wave * G + (lane >> d.lr_log2);
-    if (wave * G >= d.ntasks) return;
+    if (wave * G >= d.nrowtasks) return;
     const int l = lane & ((1 << d.lr_log2) - 1);
-    const bool task_ok = task < d.ntasks;
+    const bool task_ok = task < d.nrowtasks;
     const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
     const int vc = task_ok ? task % vchunks : 0;
     const int segi = task_ok ? task / vchunks : 0;

@@ -41,10 +41,28 @@ namespace {
 
 __device__ __forceinline__ int wrap_row(int r, int nz) { return r < 0 ? r + nz : (r >= nz ? r - nz : r); }
 
-// Sum over the lanes of a row group (xor butterfly: every lane ends with the
-// same bits, since IEEE addition is commutative).
+// Cross-lane move of an FP64 value with a fixed DPP pattern (two 32-bit
+// halves); lanes of rows outside ROW_MASK receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 2^lr_log2 lanes of a row group, entirely in VALU cross-lane
+// moves: pairs and quads (quad_perm), eights (row_half_mirror) and sixteens
+// (row_mirror) leave every lane of a 16-lane row with the same total; rows are
+// then combined with row_bcast15 / row_bcast31.  The group total ends in the
+// group's last lane; the association order depends only on lr_log2.
 __device__ __forceinline__ double group_sum(double x, int lr_log2) {
-    for (int off = (1 << lr_log2) >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+    if (lr_log2 >= 1) x += dpp_f64<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+    if (lr_log2 >= 2) x += dpp_f64<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+    if (lr_log2 >= 3) x += dpp_f64<0x141, 0xF>(x);  // row_half_mirror
+    if (lr_log2 >= 4) x += dpp_f64<0x140, 0xF>(x);  // row_mirror
+    if (lr_log2 >= 5) x += dpp_f64<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+    if (lr_log2 >= 6) x += dpp_f64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
     return x;
 }
 
@@ -132,21 +150,8 @@ __device__ __forceinline__ void minus_i_commutator(double h3, double hr, double 
     ci = ad * hr - h3 * br;
 }
 
-// Row-moment integrands of D = g rho - alpha gbar rhobar^* for one bin:
-// (D_ee - D_xx, Re D_ex, Im D_ex) and the same times v.
-__device__ __forceinline__ void moment_terms(const double o[8], double g, double ag, double v, double m[kMomQ]) {
-    const double d0 = g * (o[0] - o[1]) - ag * (o[4] - o[5]);
-    const double d1 = g * o[2] - ag * o[6];
-    const double d2 = g * o[3] + ag * o[7];
-    m[0] = d0;
-    m[1] = d1;
-    m[2] = d2;
-    m[3] = v * d0;
-    m[4] = v * d1;
-    m[5] = v * d2;
-}
-
-// Reduce the per-lane integrands over the group and let lane 0 write them.
+// Reduce the per-lane integrands over the group; the writer is the group's
+// last lane, which holds the totals.
 __device__ __forceinline__ void write_row_moments(double m[kMomQ], int lr_log2, bool writer, double *dst) {
 #pragma unroll
     for (int q = 0; q < kMomQ; ++q) m[q] = group_sum(m[q], lr_log2);
@@ -162,203 +167,300 @@ __device__ __forceinline__ T load_as(const void *base, size_t idx, bool f32) {
     return (T)(static_cast<const double *>(base)[idx]);
 }
 
-// One row group: task -> (segment, 64-bin chunk); lane l of the group owns bin
-// j = 64*chunk + l.  All lanes of a group run the same number of iterations.
-template <int SCHEME, int FORM>
-__device__ __forceinline__ void stage_group(const InstDesc &d, int stage, int task, int l) {
+// Byte-offset loads and stores from a wave-uniform base: the per-lane offset
+// is 32 bits (planes are limited to 2^29 cells), so the address is formed by
+// the memory unit from a scalar base plus one VGPR.
+template <typename T>
+__device__ __forceinline__ T ld(const char *base, uint32_t off) {
+    return *reinterpret_cast<const T *>(base + off);
+}
+template <typename T>
+__device__ __forceinline__ void st(char *base, uint32_t off, T v) {
+    *reinterpret_cast<T *>(base + off) = v;
+}
+
+// Moment integrands of one species' four components for one bin: the
+// neutrino part of D = g rho - alpha gbar rhobar^* is g rho, the antineutrino
+// part -alpha gbar rhobar^*, so (D_ee - D_xx, Re D_ex, Im D_ex) receive
+// (ca (o0 - o1), ca o2, cb o3) with ca = cb = g, or ca = -alpha gbar, cb = +alpha gbar.
+__device__ __forceinline__ void species_moment_terms(const double o[4], double ca, double cb, double v,
+                                                     double m[kMomQ]) {
+    const double d0 = ca * (o[0] - o[1]);
+    const double d1 = ca * o[2];
+    const double d2 = cb * o[3];
+    m[0] = d0;
+    m[1] = d1;
+    m[2] = d2;
+    m[3] = v * d0;
+    m[4] = v * d1;
+    m[5] = v * d2;
+}
+
+// Interface flux from the R window rows around it (FD: rows i-1..i+2, WENO7:
+// rows i-3..i+4); the upwind side of WENO7 follows the sign of v.
+template <int SCHEME, typename T>
+__device__ __forceinline__ T interface_flux(const T (&u)[SCHEME == 0 ? 4 : 8], T tv, bool vpos, T cv, T ce, T weps) {
+    if constexpr (SCHEME == 0) {
+        return fd_ko_flux<T>(u[0], u[1], u[2], u[3], cv, ce);
+    } else {
+        T a[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) a[q] = tv * (vpos ? u[q] : u[7 - q]);
+        return weno7_flux<T>(a[0], a[1], a[2], a[3], a[4], a[5], a[6], weps);
+    }
+}
+
+// Task numbering: the first d.tps tasks are neutrino groups, the next d.tps
+// antineutrino groups; within a species, task = segment * vchunks + chunk.
+// d.tps is padded to a multiple of the groups per wave, so a wave never mixes
+// species and its component planes are wave-uniform.
+struct GroupGeom {
+    int sp, vc, segi, j, jl, z0, z1;
+    bool task_ok, lane_on;
+};
+
+__device__ __forceinline__ GroupGeom group_geom(const InstDesc &d, int task, int l) {
+    GroupGeom q;
+    q.sp = task >= d.tps ? 1 : 0;
+    const int t2 = task - q.sp * d.tps;
+    q.task_ok = task < d.ntasks && t2 < d.nrowtasks;
+    q.vc = q.task_ok ? t2 % d.vchunks : 0;
+    q.segi = q.task_ok ? t2 / d.vchunks : 0;
+    q.j = q.vc * kWave + l;
+    q.lane_on = q.task_ok && q.j < d.nv;
+    q.jl = q.j < d.nv ? q.j : d.nv - 1;
+    q.z0 = q.segi * d.seg;
+    q.z1 = q.task_ok ? min(d.nz, q.z0 + d.seg) : q.z0;
+    return q;
+}
+
+// One row group of one species: march down the segment in chunks of B rows.
+// All loads of a chunk (B new window rows, plus the FP64 operands of the B
+// rows' stage combine) are issued before any of its arithmetic.
+template <int SCHEME, int FORM, int STAGE, int B>
+__device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q, int l) {
+    constexpr int stage = STAGE;
+    constexpr bool IN32 = FORM == 1 && STAGE == 2;  // Y3 of the FP32 form is stored in FP32
     using T = typename std::conditional<FORM == 0, double, float>::type;
-    constexpr int R = SCHEME == 0 ? 4 : 8;  // window rows i-H+1 .. i+H
+    using TI = typename std::conditional<IN32, float, double>::type;
+    constexpr int R = SCHEME == 0 ? 4 : 8;  // window rows of one interface flux
     constexpr int H = R / 2;
+    constexpr int NW = R + B - 1;           // window rows held during a chunk
+    constexpr int NC = 4;                   // components of one species
 
-    const bool task_ok = task < d.ntasks;
     const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
-    const int vc = task_ok ? task % vchunks : 0;
-    const int segi = task_ok ? task / vchunks : 0;
-    const int j = vc * kWave + l;
-    const bool lane_on = task_ok && (j < nv);
-    const int jl = j < nv ? j : nv - 1;
-    const int z0 = segi * d.seg;
-    const int z1 = task_ok ? min(nz, z0 + d.seg) : z0;
-
+    const int sp = q.sp, z0 = q.z0, z1 = q.z1, jl = q.jl;
     const double v = d.vel[jl];
-    const double g = lane_on ? d.g[jl] : 0.0;
-    const double ag = lane_on ? d.agb[jl] : 0.0;
+    const double gl = q.lane_on ? d.g[jl] : 0.0;
+    const double agl = q.lane_on ? d.agb[jl] : 0.0;
+    const double ca = sp ? -agl : gl, cb = sp ? agl : gl;
+    const double sgn = sp ? -1.0 : 1.0;
     const T tv = (T)v;
     const T cv = (T)(v * (1.0 / 12.0));
     const T ce = (T)d.ko16;
     const T weps = (T)d.weno_eps;
     const bool vpos = v > 0.0;
 
-    // stage-dependent buffers
-    const void *in;
-    bool in_f32 = false;
-    if (stage == 0) in = d.y;
-    else if (stage == 2) { in = d.yb; in_f32 = (FORM == 1); }
-    else in = d.ya;
+    const size_t plane = (size_t)nz * nv;
+    const int cofs = sp * NC;
+    // stage input and the operands of the combine (wave-uniform bases)
+    const void *in = stage == 0 ? (const void *)d.y : (stage == 2 ? d.yb : d.ya);
+    const char *inb = static_cast<const char *>(in) + (size_t)cofs * plane * sizeof(TI);
+    const char *yb64 = reinterpret_cast<const char *>(d.y) + (size_t)cofs * plane * sizeof(double);
+    const char *accb = reinterpret_cast<const char *>(d.acc) + (size_t)cofs * plane * sizeof(double);
+    const char *yab = static_cast<const char *>(d.ya) + (size_t)cofs * plane * sizeof(double);
+    constexpr uint32_t out_es = (STAGE == 1 && FORM == 1) ? 4 : 8;  // element size of the stage output
+    char *outb = STAGE == 0 ? static_cast<char *>(d.ya)
+               : STAGE == 1 ? static_cast<char *>(d.yb)
+               : STAGE == 2 ? static_cast<char *>(d.ya) : reinterpret_cast<char *>(d.y);
+    outb += (size_t)cofs * plane * out_es;
+    char *accw = reinterpret_cast<char *>(d.acc) + (size_t)cofs * plane * sizeof(double);
+    const uint32_t pin = (uint32_t)(plane * sizeof(TI));   // plane strides in bytes
+    const uint32_t p64 = (uint32_t)(plane * sizeof(double));
+    const uint32_t pout = (uint32_t)(plane * out_es);
     // (selects rather than an indexed load keep the descriptor in scalar registers)
     const double *m_in = stage == 0 ? d.mom[0] : stage == 1 ? d.mom[1] : stage == 2 ? d.mom[2] : d.mom[3];
     double *m_out = stage == 0 ? d.mom[1] : stage == 1 ? d.mom[2] : stage == 2 ? d.mom[3] : d.mom[0];
+    // which FP64 operands the combine reads: aux0 = y (stages 1-3, and stage 1 of
+    // the FP32 form) or acc (stage 4); aux1 = the FP64 stage input (FP32 form)
+    constexpr bool need_aux0 = (STAGE != 0) || (FORM == 1);
+    const char *aux0b = STAGE == 3 ? accb : yb64;
+    constexpr bool need_aux1 = (FORM == 1) && (STAGE == 1 || STAGE == 3);
 
     const double dz_inv = d.dz_inv, dt = d.dt, hdt = 0.5 * d.dt, dt6 = d.dt * (1.0 / 6.0);
     const double third = 1.0 / 3.0;
     const double mudv = d.mudv, h3vac = d.h3vac, hexvac = d.hexvac, lam = d.lam;
 
-    const size_t plane = (size_t)nz * nv;
-    T w[8][R];
-    T fprev[8];
+    auto load_row = [&](int row, T (&dst)[NC]) {
+        const uint32_t off = (uint32_t)(row * nv + jl) * (uint32_t)sizeof(TI);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) dst[c] = (T)ld<TI>(inb + (size_t)c * pin, off);
+    };
 
-    // prologue: rows z0-H .. z0+H-2 into slots 0 .. R-2
+    T w[NC][NW];
+    T fprev[NC];
+    {
+        // prologue: slots 0..R-2 hold rows z0-H+1 .. z0+H-1; the row below forms F_{z0-1/2}
+        T low[NC];
+        load_row(wrap_row(z0 - H, nz), low);
 #pragma unroll
-    for (int m = 0; m < R - 1; ++m) {
-        const int row = wrap_row(z0 - H + m, nz);
-        const size_t at = (size_t)row * nv + jl;
+        for (int m = 0; m < R - 1; ++m) {
+            T tmp[NC];
+            load_row(wrap_row(z0 - H + 1 + m, nz), tmp);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) w[c][m] = load_as<T>(in, c * plane + at, in_f32);
+            for (int c = 0; c < NC; ++c) w[c][m] = tmp[c];
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            T u[R];
+            u[0] = low[c];
+#pragma unroll
+            for (int m = 1; m < R; ++m) u[m] = w[c][m - 1];
+            fprev[c] = interface_flux<SCHEME, T>(u, tv, vpos, cv, ce, weps);
+        }
     }
 
-    const int iters = d.seg + 1;  // the first iteration only forms the left flux of row z0
-    for (int base = 0; base < iters; base += R) {
+    const int nparts = 2 * vchunks;
+    const bool wave_row = d.lr_log2 == 6;  // one row group per wave: the row is wave-uniform
+    for (int i0 = z0; i0 < z0 + d.seg; i0 += B) {
+        // ---- loads of the chunk -------------------------------------------------
+        // moment partials of the B input rows first (scalar loads when the row is
+        // wave-uniform), so that waiting for them never waits for the window
+        double S[B][kMomQ];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int it = base + k;
-            if (it >= iters) break;
-            const int i = z0 - 1 + it;  // this iteration forms F_{i+1/2} and produces row i
-            {
-                const int snew = (k + R - 1) % R;
-                // rows past the end of a ragged segment are not produced: keep
-                // their look-ahead on the last produced row (stays in [0, 2 nz))
-                const int ahead = min(i + H, z1 - 1 + H);
-                const size_t at = (size_t)wrap_row(ahead, nz) * nv + jl;
+        for (int b = 0; b < B; ++b) {
+            int irow = min(i0 + b, nz - 1);
+            if (wave_row) irow = __builtin_amdgcn_readfirstlane(irow);
+            const double *mp = m_in + (size_t)irow * nparts * kMomQ;
 #pragma unroll
-                for (int c = 0; c < 8; ++c) w[c][snew] = load_as<T>(in, c * plane + at, in_f32);
+            for (int k = 0; k < kMomQ; ++k) S[b][k] = mp[k] + mp[kMomQ + k];
+            for (int p = 2; p < nparts; ++p) {
+#pragma unroll
+                for (int k = 0; k < kMomQ; ++k) S[b][k] += mp[p * kMomQ + k];
             }
-            T fnew[8];
+        }
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                if (SCHEME == 0) {
-                    fnew[c] = fd_ko_flux<T>(w[c][(k + 0) % R], w[c][(k + 1) % R], w[c][(k + 2) % R],
-                                            w[c][(k + 3) % R], cv, ce);
+        for (int b = 0; b < B; ++b) {
+            // rows past a ragged segment end are not produced; their look-ahead
+            // stays on the last produced row (always inside [0, 2 nz))
+            const int ahead = min(i0 + b + H, z1 - 1 + H);
+            T tmp[NC];
+            load_row(wrap_row(ahead, nz), tmp);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) w[c][R - 1 + b] = tmp[c];
+        }
+        double aux0[B][NC], aux1[B][NC];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int irow = min(i0 + b, nz - 1);
+            const uint32_t off = (uint32_t)(irow * nv + jl) * 8u;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if constexpr (need_aux0) aux0[b][c] = ld<double>(aux0b + (size_t)c * p64, off);
+                if constexpr (need_aux1) aux1[b][c] = ld<double>(yab + (size_t)c * p64, off);
+            }
+        }
+        // ---- the B rows of the chunk ---------------------------------------------
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = i0 + b;
+            const bool row_in = i < z1;
+            const int irow = min(i, nz - 1);
+            // H of this row and bin from the moment partials of the stage input
+            const double A0 = S[b][0] - v * S[b][3], A1 = S[b][1] - v * S[b][4], A2 = S[b][2] - v * S[b][5];
+            const double h3 = h3vac + sgn * (lam + mudv * A0);
+            const double hr = hexvac + sgn * (mudv * A1);
+            const double hi = mudv * A2;
+            double u[NC], kk[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) u[c] = (double)w[c][b + H - 1];
+            minus_i_commutator(h3, hr, hi, u[0], u[1], u[2], u[3], kk[0], kk[1], kk[2], kk[3]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                T uu[R];
+#pragma unroll
+                for (int m = 0; m < R; ++m) uu[m] = w[c][b + m];
+                const T fnew = interface_flux<SCHEME, T>(uu, tv, vpos, cv, ce, weps);
+                kk[c] -= ((double)fnew - (double)fprev[c]) * dz_inv;
+                fprev[c] = fnew;
+            }
+            // stage combine
+            double o[NC];
+            const uint32_t off64 = (uint32_t)(irow * nv + jl) * 8u;
+            const uint32_t offo = (uint32_t)(irow * nv + jl) * out_es;
+            const bool on = row_in && q.lane_on;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if constexpr (STAGE == 0) {
+                    if constexpr (FORM == 0) o[c] = u[c] + hdt * kk[c];
+                    else o[c] = aux0[b][c] + hdt * kk[c];
+                } else if constexpr (STAGE == 1) {
+                    double y2;
+                    if constexpr (FORM == 0) y2 = u[c];
+                    else y2 = aux1[b][c];
+                    o[c] = aux0[b][c] + hdt * kk[c];
+                    if (on) st<double>(accw + (size_t)c * p64, off64, ((aux0[b][c] + y2) + dt * kk[c]) * third);
+                } else if constexpr (STAGE == 2) {
+                    o[c] = aux0[b][c] + dt * kk[c];
                 } else {
-                    // rows i-3..i+4 are window slots (k+0..7) % R; upwind orientation by the sign of v
-                    T a[7];
-#pragma unroll
-                    for (int q = 0; q < 7; ++q) {
-                        const T up = w[c][(k + q) % R];
-                        const T dn = w[c][(k + 7 - q) % R];
-                        a[q] = tv * (vpos ? up : dn);
-                    }
-                    fnew[c] = weno7_flux<T>(a[0], a[1], a[2], a[3], a[4], a[5], a[6], weps);
+                    double y4;
+                    if constexpr (FORM == 0) y4 = u[c];
+                    else y4 = aux1[b][c];
+                    o[c] = (aux0[b][c] + y4 * third) + dt6 * kk[c];
                 }
-            }
-            if (it > 0) {
-                const bool row_in = i < z1;
-                const bool on = row_in && lane_on;
-                const int irow = min(i, nz - 1);
-                const size_t at = (size_t)irow * nv + jl;
-                // Hamiltonian of this row and bin (eq:ham; vacuum and matter terms per Sec. 2)
-                double S[kMomQ] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                for (int p = 0; p < vchunks; ++p) {
-                    const double *mp = m_in + ((size_t)irow * vchunks + p) * kMomQ;
-#pragma unroll
-                    for (int q = 0; q < kMomQ; ++q) S[q] += mp[q];
-                }
-                const double A0 = S[0] - v * S[3], A1 = S[1] - v * S[4], A2 = S[2] - v * S[5];
-                const double hn3 = h3vac + lam + mudv * A0, hnr = hexvac + mudv * A1, hni = mudv * A2;
-                const double hb3 = h3vac - lam - mudv * A0, hbr = hexvac - mudv * A1, hbi = mudv * A2;
-                const int sc = (k + H - 1) % R;
-                double u[8];
-#pragma unroll
-                for (int c = 0; c < 8; ++c) u[c] = (double)w[c][sc];
-                double kk[8];
-                minus_i_commutator(hn3, hnr, hni, u[0], u[1], u[2], u[3], kk[0], kk[1], kk[2], kk[3]);
-                minus_i_commutator(hb3, hbr, hbi, u[4], u[5], u[6], u[7], kk[4], kk[5], kk[6], kk[7]);
-#pragma unroll
-                for (int c = 0; c < 8; ++c) kk[c] -= ((double)fnew[c] - (double)fprev[c]) * dz_inv;
-
-                double o[8];
-#pragma unroll
-                for (int c = 0; c < 8; ++c) o[c] = 0.0;
                 if (on) {
-                    if (stage == 0) {
-                        double *ya = static_cast<double *>(d.ya);
-#pragma unroll
-                        for (int c = 0; c < 8; ++c) {
-                            const double yc = FORM == 0 ? u[c] : d.y[c * plane + at];
-                            o[c] = yc + hdt * kk[c];
-                            ya[c * plane + at] = o[c];
-                        }
-                    } else if (stage == 1) {
-#pragma unroll
-                        for (int c = 0; c < 8; ++c) {
-                            const double yv = d.y[c * plane + at];
-                            const double y2 = FORM == 0 ? u[c] : static_cast<const double *>(d.ya)[c * plane + at];
-                            o[c] = yv + hdt * kk[c];
-                            d.acc[c * plane + at] = ((yv + y2) + dt * kk[c]) * third;
-                            if (FORM == 0) static_cast<double *>(d.yb)[c * plane + at] = o[c];
-                            else static_cast<float *>(d.yb)[c * plane + at] = (float)o[c];
-                        }
-                    } else if (stage == 2) {
-                        double *ya = static_cast<double *>(d.ya);
-#pragma unroll
-                        for (int c = 0; c < 8; ++c) {
-                            const double yv = d.y[c * plane + at];
-                            o[c] = yv + dt * kk[c];
-                            ya[c * plane + at] = o[c];
-                        }
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < 8; ++c) {
-                            const double av = d.acc[c * plane + at];
-                            const double y4 = FORM == 0 ? u[c] : static_cast<const double *>(d.ya)[c * plane + at];
-                            o[c] = (av + y4 * third) + dt6 * kk[c];
-                            d.y[c * plane + at] = o[c];
-                        }
-                    }
-                    if (FORM == 1) {
-#pragma unroll
-                        for (int c = 0; c < 8; ++c) o[c] = (double)(float)o[c];  // the next stage sees FP32 values
-                    }
+                    if constexpr (out_es == 8) st<double>(outb + (size_t)c * pout, offo, o[c]);
+                    else st<float>(outb + (size_t)c * pout, offo, (float)o[c]);
                 }
-                double mt[kMomQ];
-                moment_terms(o, g, ag, v, mt);
-                write_row_moments(mt, d.lr_log2, row_in && l == 0,
-                                  m_out + ((size_t)irow * vchunks + vc) * kMomQ);
+                if (FORM == 1) o[c] = (double)(float)o[c];  // the next stage sees FP32 values
+                if (!on) o[c] = 0.0;
             }
+            double mt[kMomQ];
+            species_moment_terms(o, ca, cb, v, mt);
+            write_row_moments(mt, d.lr_log2, row_in && l == (1 << d.lr_log2) - 1,
+                              m_out + (((size_t)irow * vchunks + q.vc) * 2 + sp) * kMomQ);
+        }
+        // ---- slide the window by B rows -------------------------------------------
 #pragma unroll
-            for (int c = 0; c < 8; ++c) fprev[c] = fnew[c];
+        for (int m = 0; m < R - 1; ++m) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) w[c][m] = w[c][m + B];
         }
     }
 }
 
-// Moments of the stage-1 input (the state y) for a freshly set state.
+template <int SCHEME, int FORM, int STAGE>
+__device__ __forceinline__ void stage_group(const InstDesc &d, int task, int l) {
+    const GroupGeom q = group_geom(d, task, l);
+    stage_body<SCHEME, FORM, STAGE, kChunkRows[SCHEME]>(d, q, l);
+}
+
+// Moment partials of the stage-1 input (the state y) for a freshly set state,
+// with exactly the arithmetic the stage-4 producer uses.
 template <int FORM>
 __device__ __forceinline__ void moments_group(const InstDesc &d, int task, int l) {
-    const bool task_ok = task < d.ntasks;
-    const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
-    const int vc = task_ok ? task % vchunks : 0;
-    const int segi = task_ok ? task / vchunks : 0;
-    const int j = vc * kWave + l;
-    const bool lane_on = task_ok && (j < nv);
-    const int jl = j < nv ? j : nv - 1;
-    const int z0 = segi * d.seg;
-    const int z1 = task_ok ? min(nz, z0 + d.seg) : z0;
-    const double v = d.vel[jl];
-    const double g = lane_on ? d.g[jl] : 0.0;
-    const double ag = lane_on ? d.agb[jl] : 0.0;
+    const GroupGeom q = group_geom(d, task, l);
+    const int nz = d.nz, nv = d.nv;
+    const double v = d.vel[q.jl];
+    const double gl = q.lane_on ? d.g[q.jl] : 0.0;
+    const double agl = q.lane_on ? d.agb[q.jl] : 0.0;
+    const double ca = q.sp ? -agl : gl, cb = q.sp ? agl : gl;
     const size_t plane = (size_t)nz * nv;
-    for (int i = z0; i < z0 + d.seg; ++i) {
-        const bool row_in = i < z1;
+    const double *yb = d.y + (size_t)q.sp * 4 * plane;
+    for (int i = q.z0; i < q.z0 + d.seg; ++i) {
+        const bool row_in = i < q.z1;
         const int irow = min(i, nz - 1);
-        const size_t at = (size_t)irow * nv + jl;
-        double o[8];
+        const size_t at = (size_t)irow * nv + q.jl;
+        double o[4];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            double x = (row_in && lane_on) ? d.y[c * plane + at] : 0.0;
+        for (int c = 0; c < 4; ++c) {
+            const double x = (row_in && q.lane_on) ? yb[c * plane + at] : 0.0;
             o[c] = FORM == 1 ? (double)(float)x : x;
         }
         double mt[kMomQ];
-        moment_terms(o, g, ag, v, mt);
-        write_row_moments(mt, d.lr_log2, row_in && l == 0, d.mom[0] + ((size_t)irow * vchunks + vc) * kMomQ);
+        species_moment_terms(o, ca, cb, v, mt);
+        write_row_moments(mt, d.lr_log2, row_in && l == (1 << d.lr_log2) - 1,
+                          d.mom[0] + (((size_t)irow * d.vchunks + q.vc) * 2 + q.sp) * kMomQ);
     }
 }
 
@@ -372,15 +474,15 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk) {
     return start + kk;
 }
 
-template <int SCHEME, int FORM>
-__global__ __launch_bounds__(kWave *kWavesPerBlock) void stage_kernel(InstDesc d, int stage) {
+template <int SCHEME, int FORM, int STAGE>
+__global__ __launch_bounds__(kWave *kWavesPerBlock) void stage_kernel(InstDesc d) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int wave = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & (kWave - 1);
     const int G = kWave >> d.lr_log2;
     const int task = wave * G + (lane >> d.lr_log2);
     if (wave * G >= d.ntasks) return;  // whole wave idle (uniform)
-    stage_group<SCHEME, FORM>(d, stage, task, lane & ((1 << d.lr_log2) - 1));
+    stage_group<SCHEME, FORM, STAGE>(d, task, lane & ((1 << d.lr_log2) - 1));
 }
 
 template <int FORM>
@@ -398,17 +500,17 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void moments_init_kernel(Ins
 // (the list is sorted by decreasing cost on the host).  Every wave reads its
 // instance descriptor, then runs the same group code as a single instance.
 // One kernel per scheme, so each gets its own register budget.
-template <int SCHEME, int FORM>
+template <int SCHEME, int FORM, int STAGE>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void batch_stage_kernel(const InstDesc *__restrict__ descs,
                                                                            const WaveTask *__restrict__ tasks,
-                                                                           int nwt, int stage) {
+                                                                           int nwt) {
     const int nwaves = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & (kWave - 1);
     const int first = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
     for (int wt = first; wt < nwt; wt += nwaves) {
         const WaveTask t = tasks[wt];
         const InstDesc &d = descs[t.inst];
-        stage_group<SCHEME, FORM>(d, stage, t.task0 + (lane >> d.lr_log2), lane & ((1 << d.lr_log2) - 1));
+        stage_group<SCHEME, FORM, STAGE>(d, t.task0 + (lane >> d.lr_log2), lane & ((1 << d.lr_log2) - 1));
     }
 }
 
@@ -422,16 +524,41 @@ int blocks_for(const InstDesc &d) {
     return (waves + kWavesPerBlock - 1) / kWavesPerBlock;
 }
 
-hipError_t launch_stage(const InstDesc &d, int stage, int blocks, hipStream_t st) {
-    const dim3 grid(blocks), block(kWave * kWavesPerBlock);
-    if (d.scheme == 0) {
-        if (d.form == 0) hipLaunchKernelGGL((stage_kernel<0, 0>), grid, block, 0, st, d, stage);
-        else hipLaunchKernelGGL((stage_kernel<0, 1>), grid, block, 0, st, d, stage);
-    } else {
-        if (d.form == 0) hipLaunchKernelGGL((stage_kernel<1, 0>), grid, block, 0, st, d, stage);
-        else hipLaunchKernelGGL((stage_kernel<1, 1>), grid, block, 0, st, d, stage);
+int row_blocks_for(const InstDesc &d) {
+    const int G = groups_per_wave(d);
+    const int waves = (d.nrowtasks + G - 1) / G;
+    return (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+}
+
+namespace {
+template <int SCHEME, int FORM>
+hipError_t launch_stage_t(const InstDesc &d, int stage, dim3 grid, dim3 block, hipStream_t st) {
+    switch (stage) {
+        case 0: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 0>), grid, block, 0, st, d); break;
+        case 1: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 1>), grid, block, 0, st, d); break;
+        case 2: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 2>), grid, block, 0, st, d); break;
+        default: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 3>), grid, block, 0, st, d); break;
     }
     return hipGetLastError();
+}
+template <int SCHEME, int FORM>
+hipError_t launch_batch_t(const InstDesc *dd, const WaveTask *tk, int nwt, int stage, dim3 grid, dim3 block,
+                          hipStream_t st) {
+    switch (stage) {
+        case 0: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 0>), grid, block, 0, st, dd, tk, nwt); break;
+        case 1: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 1>), grid, block, 0, st, dd, tk, nwt); break;
+        case 2: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 2>), grid, block, 0, st, dd, tk, nwt); break;
+        default: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 3>), grid, block, 0, st, dd, tk, nwt); break;
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_stage(const InstDesc &d, int stage, int blocks, hipStream_t st) {
+    const dim3 grid(blocks), block(kWave * kWavesPerBlock);
+    if (d.scheme == 0) return d.form == 0 ? launch_stage_t<0, 0>(d, stage, grid, block, st)
+                                          : launch_stage_t<0, 1>(d, stage, grid, block, st);
+    return d.form == 0 ? launch_stage_t<1, 0>(d, stage, grid, block, st) : launch_stage_t<1, 1>(d, stage, grid, block, st);
 }
 
 hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st) {
@@ -444,14 +571,10 @@ hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st) {
 hipError_t launch_batch_stage(const InstDesc *d_descs, const WaveTask *d_tasks, int nwt, int scheme, int form,
                               int stage, int blocks, hipStream_t st) {
     const dim3 grid(blocks), block(kWave * kWavesPerBlock);
-    if (scheme == 0) {
-        if (form == 0) hipLaunchKernelGGL((batch_stage_kernel<0, 0>), grid, block, 0, st, d_descs, d_tasks, nwt, stage);
-        else hipLaunchKernelGGL((batch_stage_kernel<0, 1>), grid, block, 0, st, d_descs, d_tasks, nwt, stage);
-    } else {
-        if (form == 0) hipLaunchKernelGGL((batch_stage_kernel<1, 0>), grid, block, 0, st, d_descs, d_tasks, nwt, stage);
-        else hipLaunchKernelGGL((batch_stage_kernel<1, 1>), grid, block, 0, st, d_descs, d_tasks, nwt, stage);
-    }
-    return hipGetLastError();
+    if (scheme == 0) return form == 0 ? launch_batch_t<0, 0>(d_descs, d_tasks, nwt, stage, grid, block, st)
+                                      : launch_batch_t<0, 1>(d_descs, d_tasks, nwt, stage, grid, block, st);
+    return form == 0 ? launch_batch_t<1, 0>(d_descs, d_tasks, nwt, stage, grid, block, st)
+                     : launch_batch_t<1, 1>(d_descs, d_tasks, nwt, stage, grid, block, st);
 }
 
 }  // namespace cosenu
