@@ -151,6 +151,7 @@ void fill_desc_constants(const cosenu_params &p, InstDesc &d) {
     d.lam = p.lambda;
     d.ko16 = p.ko_eps / 16.0;
     d.weno_eps = p.weno_eps;
+    d.ps = (size_t)p.nz * p.nv + kPlanePad;
     set_shape(d, default_seg_rows(p.nz, p.nv));
 }
 
@@ -318,8 +319,9 @@ int compute_conserved(cosenu_sim *s, cosenu_conserved_t *out) {
 }
 
 int upload_state(cosenu_sim *s, const double *host) {
-    const size_t n = (size_t)8 * s->d.nz * s->d.nv;
-    HIPCHK(s, hipMemcpyAsync(s->d.y, host, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    const size_t row = (size_t)s->d.nz * s->d.nv * sizeof(double);
+    HIPCHK(s, hipMemcpy2DAsync(s->d.y, s->d.ps * sizeof(double), host, row, row, 8, hipMemcpyHostToDevice,
+                               s->stream));
     HIPCHK(s, launch_moments_init(s->d, blocks_for(s->d), s->stream));
     cosenu_conserved_t c;
     int rc = compute_conserved(s, &c);
@@ -393,8 +395,8 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) {
 
     const int nz = p->nz, nv = p->nv;
     const size_t cells = (size_t)nz * nv;
-    const size_t f64 = 8 * cells * sizeof(double);
-    const size_t ybbytes = 8 * cells * (p->precision == COSENU_FP64 ? sizeof(double) : sizeof(float));
+    const size_t f64 = 8 * s->d.ps * sizeof(double);
+    const size_t ybbytes = 8 * s->d.ps * (p->precision == COSENU_FP64 ? sizeof(double) : sizeof(float));
     void *ptr = nullptr;
     int rc;
     if ((rc = sim_alloc(s, &ptr, f64))) return fail(rc);
@@ -474,7 +476,8 @@ int cosenu_get_state(cosenu_sim *s, double *out, size_t n) {
     SIM_CHECK(s);
     const size_t need = (size_t)8 * s->d.nz * s->d.nv;
     if (!out || n < need) return COSENU_EINVAL;
-    HIPCHK(s, hipMemcpyAsync(out, s->d.y, need * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    const size_t row = (size_t)s->d.nz * s->d.nv * sizeof(double);
+    HIPCHK(s, hipMemcpy2DAsync(out, row, s->d.y, s->d.ps * sizeof(double), row, 8, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     return COSENU_OK;
 }

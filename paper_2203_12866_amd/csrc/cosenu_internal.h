@@ -13,7 +13,9 @@ constexpr int kWavesPerBlock = 4;   // stage kernels run 256-thread workgroups
 constexpr int kMomQ = 6;            // reduced quantities per row and part:
                                     //   sum D3, sum ReDex, sum ImDex, and the same times v
 constexpr int kDiagQ = 12;
-constexpr int kChunkRows[2] = {4, 2};  // rows per load chunk of the stage kernels: FD, WENO7          // per-task partials of the conserved-quantity kernel
+constexpr int kChunkRows[2] = {2, 1};  // rows per load chunk of the stage kernels: FD, WENO7
+constexpr int kPlanePad = 544;         // elements between planes beyond nz*nv (4352 B in FP64, 2176 B
+                                       // in FP32: 128-byte aligned, off the power-of-two strides)          // per-task partials of the conserved-quantity kernel
 
 // Everything one stage launch needs about one simulation.  Passed by value to
 // the single-instance kernels and stored in device memory for the batch.
@@ -36,11 +38,12 @@ struct InstDesc {
     double ko16;       // ko_eps / 16
     double weno_eps;
     double dv;
+    size_t ps;         // plane stride in elements: nz * nv + kPlanePad
     const double *g;   // g_nu per bin                       [nv]
     const double *gb;  // g_nubar per bin                    [nv]
     const double *agb; // alpha * g_nubar per bin            [nv]
     const double *vel; // bin midpoints                      [nv]
-    double *y;         // state, FP64                        [8][nz][nv]
+    double *y;         // state, FP64                        [8][ps], plane = [nz][nv]
     double *acc;       // RK4 accumulator, FP64              [8][nz][nv]
     void *ya;          // Y2 / Y4 stage values, FP64         [8][nz][nv]
     void *yb;          // Y3 stage values, FP64 or FP32      [8][nz][nv]

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void diag_kernel(InstDesc d,
     const int z0 = segi * d.seg;
     const int z1 = task_ok ? min(nz, z0 + d.seg) : z0;
     const double g = d.g[jl], gb = d.gb[jl], ag = d.agb[jl];
-    const size_t plane = (size_t)nz * nv;
+    const size_t plane = d.ps;
     double a[kDiagQ];
 #pragma unroll
     for (int q = 0; q < kDiagQ; ++q) a[q] = 0.0;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void moments_out_kernel(Inst
     const int z0 = segi * d.seg;
     const int z1 = task_ok ? min(nz, z0 + d.seg) : z0;
     const double g = d.g[jl], ag = d.agb[jl], v = d.vel[jl];
-    const size_t plane = (size_t)nz * nv;
+    const size_t plane = d.ps;
     for (int i = z0; i < z0 + d.seg; ++i) {
         const bool row_in = i < z1;
         const int irow = min(i, nz - 1);

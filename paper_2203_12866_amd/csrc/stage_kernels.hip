@@ -5,6 +5,8 @@
 //
 // Layout: every array is 8 real planes [c][z][v] with v fastest, so a z row of
 // one component is nv contiguous values and a wavefront reads whole rows.
+// Planes are d.ps elements apart (nz*nv plus a pad that keeps concurrently
+// streamed planes off a power-of-two stride).
 //
 // Work decomposition: the v bins of a row are spread over a "row group" of
 // LR = min(64, pow2ceil(nv)) lanes (nv > 64: several 64-bin chunks, each its own
@@ -234,19 +236,32 @@ __device__ __forceinline__ GroupGeom group_geom(const InstDesc &d, int task, int
     return q;
 }
 
-// One row group of one species: march down the segment in chunks of B rows.
-// All loads of a chunk (B new window rows, plus the FP64 operands of the B
-// rows' stage combine) are issued before any of its arithmetic.
+// Everything one chunk of B rows needs from memory, loaded ahead of use.
+template <typename T, int B, int NC, bool AUX0, bool AUX1>
+struct ChunkBuf {
+    T nw[NC][B];           // the B window rows entering with this chunk
+    double a0[B][NC];      // y (or acc in stage 4) of the B produced rows
+    double a1[B][NC];      // the FP64 stage input of the B rows (FP32 form, stages 2 and 4)
+    double S[B][kMomQ];    // summed moment partials of the B input rows
+};
+
+// One row group of one species: march down the segment in chunks of B rows,
+// software-pipelined one chunk deep.  Two chunk buffers alternate: while
+// chunk c is computed, the loads of chunk c+1 (its new window rows, the FP64
+// operands of its stage combine and its moment partials) are in flight, and
+// the arithmetic reads straight from the buffer registers so that no copy
+// forces an early wait.
 template <int SCHEME, int FORM, int STAGE, int B>
 __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q, int l) {
-    constexpr int stage = STAGE;
     constexpr bool IN32 = FORM == 1 && STAGE == 2;  // Y3 of the FP32 form is stored in FP32
     using T = typename std::conditional<FORM == 0, double, float>::type;
     using TI = typename std::conditional<IN32, float, double>::type;
     constexpr int R = SCHEME == 0 ? 4 : 8;  // window rows of one interface flux
     constexpr int H = R / 2;
-    constexpr int NW = R + B - 1;           // window rows held during a chunk
     constexpr int NC = 4;                   // components of one species
+    constexpr bool AUX0 = (STAGE != 0) || (FORM == 1);          // y, or acc in stage 4
+    constexpr bool AUX1 = (FORM == 1) && (STAGE == 1 || STAGE == 3);  // FP64 stage input
+    using Buf = ChunkBuf<T, B, NC, AUX0, AUX1>;
 
     const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
     const int sp = q.sp, z0 = q.z0, z1 = q.z1, jl = q.jl;
@@ -261,35 +276,30 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     const T weps = (T)d.weno_eps;
     const bool vpos = v > 0.0;
 
-    const size_t plane = (size_t)nz * nv;
+    const size_t plane = d.ps;  // plane stride in elements (padded)
     const int cofs = sp * NC;
-    // stage input and the operands of the combine (wave-uniform bases)
-    const void *in = stage == 0 ? (const void *)d.y : (stage == 2 ? d.yb : d.ya);
+    const void *in = STAGE == 0 ? (const void *)d.y : (STAGE == 2 ? d.yb : d.ya);
     const char *inb = static_cast<const char *>(in) + (size_t)cofs * plane * sizeof(TI);
-    const char *yb64 = reinterpret_cast<const char *>(d.y) + (size_t)cofs * plane * sizeof(double);
-    const char *accb = reinterpret_cast<const char *>(d.acc) + (size_t)cofs * plane * sizeof(double);
-    const char *yab = static_cast<const char *>(d.ya) + (size_t)cofs * plane * sizeof(double);
+    const char *aux0b = reinterpret_cast<const char *>(STAGE == 3 ? d.acc : d.y) + (size_t)cofs * plane * 8;
+    const char *aux1b = static_cast<const char *>(d.ya) + (size_t)cofs * plane * 8;
     constexpr uint32_t out_es = (STAGE == 1 && FORM == 1) ? 4 : 8;  // element size of the stage output
     char *outb = STAGE == 0 ? static_cast<char *>(d.ya)
                : STAGE == 1 ? static_cast<char *>(d.yb)
                : STAGE == 2 ? static_cast<char *>(d.ya) : reinterpret_cast<char *>(d.y);
     outb += (size_t)cofs * plane * out_es;
-    char *accw = reinterpret_cast<char *>(d.acc) + (size_t)cofs * plane * sizeof(double);
-    const uint32_t pin = (uint32_t)(plane * sizeof(TI));   // plane strides in bytes
-    const uint32_t p64 = (uint32_t)(plane * sizeof(double));
-    const uint32_t pout = (uint32_t)(plane * out_es);
-    // (selects rather than an indexed load keep the descriptor in scalar registers)
-    const double *m_in = stage == 0 ? d.mom[0] : stage == 1 ? d.mom[1] : stage == 2 ? d.mom[2] : d.mom[3];
-    double *m_out = stage == 0 ? d.mom[1] : stage == 1 ? d.mom[2] : stage == 2 ? d.mom[3] : d.mom[0];
-    // which FP64 operands the combine reads: aux0 = y (stages 1-3, and stage 1 of
-    // the FP32 form) or acc (stage 4); aux1 = the FP64 stage input (FP32 form)
-    constexpr bool need_aux0 = (STAGE != 0) || (FORM == 1);
-    const char *aux0b = STAGE == 3 ? accb : yb64;
-    constexpr bool need_aux1 = (FORM == 1) && (STAGE == 1 || STAGE == 3);
+    char *accw = reinterpret_cast<char *>(d.acc) + (size_t)cofs * plane * 8;
+    const size_t pin = plane * sizeof(TI);   // plane strides in bytes
+    const size_t p64 = plane * 8;
+    const size_t pout = plane * out_es;
+    const double *m_in = STAGE == 0 ? d.mom[0] : STAGE == 1 ? d.mom[1] : STAGE == 2 ? d.mom[2] : d.mom[3];
+    double *m_out = STAGE == 0 ? d.mom[1] : STAGE == 1 ? d.mom[2] : STAGE == 2 ? d.mom[3] : d.mom[0];
+    const int nparts = 2 * vchunks;
+    const bool wave_row = d.lr_log2 == 6;  // one row group per wave: rows are wave-uniform
 
     const double dz_inv = d.dz_inv, dt = d.dt, hdt = 0.5 * d.dt, dt6 = d.dt * (1.0 / 6.0);
     const double third = 1.0 / 3.0;
     const double mudv = d.mudv, h3vac = d.h3vac, hexvac = d.hexvac, lam = d.lam;
+    const int zend = z0 + d.seg;
 
     auto load_row = [&](int row, T (&dst)[NC]) {
         const uint32_t off = (uint32_t)(row * nv + jl) * (uint32_t)sizeof(TI);
@@ -297,46 +307,18 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         for (int c = 0; c < NC; ++c) dst[c] = (T)ld<TI>(inb + (size_t)c * pin, off);
     };
 
-    T w[NC][NW];
-    T fprev[NC];
-    {
-        // prologue: slots 0..R-2 hold rows z0-H+1 .. z0+H-1; the row below forms F_{z0-1/2}
-        T low[NC];
-        load_row(wrap_row(z0 - H, nz), low);
-#pragma unroll
-        for (int m = 0; m < R - 1; ++m) {
-            T tmp[NC];
-            load_row(wrap_row(z0 - H + 1 + m, nz), tmp);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) w[c][m] = tmp[c];
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            T u[R];
-            u[0] = low[c];
-#pragma unroll
-            for (int m = 1; m < R; ++m) u[m] = w[c][m - 1];
-            fprev[c] = interface_flux<SCHEME, T>(u, tv, vpos, cv, ce, weps);
-        }
-    }
-
-    const int nparts = 2 * vchunks;
-    const bool wave_row = d.lr_log2 == 6;  // one row group per wave: the row is wave-uniform
-    for (int i0 = z0; i0 < z0 + d.seg; i0 += B) {
-        // ---- loads of the chunk -------------------------------------------------
-        // moment partials of the B input rows first (scalar loads when the row is
-        // wave-uniform), so that waiting for them never waits for the window
-        double S[B][kMomQ];
+    // issue every load of the chunk starting at row i0
+    auto issue = [&](int i0, Buf &cb_) {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             int irow = min(i0 + b, nz - 1);
             if (wave_row) irow = __builtin_amdgcn_readfirstlane(irow);
             const double *mp = m_in + (size_t)irow * nparts * kMomQ;
 #pragma unroll
-            for (int k = 0; k < kMomQ; ++k) S[b][k] = mp[k] + mp[kMomQ + k];
+            for (int k = 0; k < kMomQ; ++k) cb_.S[b][k] = mp[k] + mp[kMomQ + k];
             for (int p = 2; p < nparts; ++p) {
 #pragma unroll
-                for (int k = 0; k < kMomQ; ++k) S[b][k] += mp[p * kMomQ + k];
+                for (int k = 0; k < kMomQ; ++k) cb_.S[b][k] += mp[p * kMomQ + k];
             }
         }
 #pragma unroll
@@ -347,44 +329,52 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
             T tmp[NC];
             load_row(wrap_row(ahead, nz), tmp);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) w[c][R - 1 + b] = tmp[c];
+            for (int c = 0; c < NC; ++c) cb_.nw[c][b] = tmp[c];
         }
-        double aux0[B][NC], aux1[B][NC];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const int irow = min(i0 + b, nz - 1);
-            const uint32_t off = (uint32_t)(irow * nv + jl) * 8u;
+            const uint32_t off = (uint32_t)(min(i0 + b, nz - 1) * nv + jl) * 8u;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                if constexpr (need_aux0) aux0[b][c] = ld<double>(aux0b + (size_t)c * p64, off);
-                if constexpr (need_aux1) aux1[b][c] = ld<double>(yab + (size_t)c * p64, off);
+                if constexpr (AUX0) cb_.a0[b][c] = ld<double>(aux0b + (size_t)c * p64, off);
+                if constexpr (AUX1) cb_.a1[b][c] = ld<double>(aux1b + (size_t)c * p64, off);
             }
         }
-        // ---- the B rows of the chunk ---------------------------------------------
+    };
+
+    T w[NC][R - 1];  // carried window rows i0-H+1 .. i0+H-1
+    T fprev[NC];     // flux at i0-1/2
+
+    // the B rows of a chunk: window row m of row i0+b is w (m < R-1-b) or the buffer
+    auto compute = [&](int i0, const Buf &cb_) {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = i0 + b;
             const bool row_in = i < z1;
             const int irow = min(i, nz - 1);
-            // H of this row and bin from the moment partials of the stage input
-            const double A0 = S[b][0] - v * S[b][3], A1 = S[b][1] - v * S[b][4], A2 = S[b][2] - v * S[b][5];
+            auto win = [&](int c, int m) -> T {  // window row i-H+1+m
+                const int k = b + m;             // index in carried ++ buffer
+                return k < R - 1 ? w[c][k] : cb_.nw[c][k - (R - 1)];
+            };
+            const double A0 = cb_.S[b][0] - v * cb_.S[b][3];
+            const double A1 = cb_.S[b][1] - v * cb_.S[b][4];
+            const double A2 = cb_.S[b][2] - v * cb_.S[b][5];
             const double h3 = h3vac + sgn * (lam + mudv * A0);
             const double hr = hexvac + sgn * (mudv * A1);
             const double hi = mudv * A2;
             double u[NC], kk[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) u[c] = (double)w[c][b + H - 1];
+            for (int c = 0; c < NC; ++c) u[c] = (double)win(c, H - 1);
             minus_i_commutator(h3, hr, hi, u[0], u[1], u[2], u[3], kk[0], kk[1], kk[2], kk[3]);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 T uu[R];
 #pragma unroll
-                for (int m = 0; m < R; ++m) uu[m] = w[c][b + m];
+                for (int m = 0; m < R; ++m) uu[m] = win(c, m);
                 const T fnew = interface_flux<SCHEME, T>(uu, tv, vpos, cv, ce, weps);
                 kk[c] -= ((double)fnew - (double)fprev[c]) * dz_inv;
                 fprev[c] = fnew;
             }
-            // stage combine
             double o[NC];
             const uint32_t off64 = (uint32_t)(irow * nv + jl) * 8u;
             const uint32_t offo = (uint32_t)(irow * nv + jl) * out_es;
@@ -393,20 +383,20 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
             for (int c = 0; c < NC; ++c) {
                 if constexpr (STAGE == 0) {
                     if constexpr (FORM == 0) o[c] = u[c] + hdt * kk[c];
-                    else o[c] = aux0[b][c] + hdt * kk[c];
+                    else o[c] = cb_.a0[b][c] + hdt * kk[c];
                 } else if constexpr (STAGE == 1) {
                     double y2;
                     if constexpr (FORM == 0) y2 = u[c];
-                    else y2 = aux1[b][c];
-                    o[c] = aux0[b][c] + hdt * kk[c];
-                    if (on) st<double>(accw + (size_t)c * p64, off64, ((aux0[b][c] + y2) + dt * kk[c]) * third);
+                    else y2 = cb_.a1[b][c];
+                    o[c] = cb_.a0[b][c] + hdt * kk[c];
+                    if (on) st<double>(accw + (size_t)c * p64, off64, ((cb_.a0[b][c] + y2) + dt * kk[c]) * third);
                 } else if constexpr (STAGE == 2) {
-                    o[c] = aux0[b][c] + dt * kk[c];
+                    o[c] = cb_.a0[b][c] + dt * kk[c];
                 } else {
                     double y4;
                     if constexpr (FORM == 0) y4 = u[c];
-                    else y4 = aux1[b][c];
-                    o[c] = (aux0[b][c] + y4 * third) + dt6 * kk[c];
+                    else y4 = cb_.a1[b][c];
+                    o[c] = (cb_.a0[b][c] + y4 * third) + dt6 * kk[c];
                 }
                 if (on) {
                     if constexpr (out_es == 8) st<double>(outb + (size_t)c * pout, offo, o[c]);
@@ -420,12 +410,41 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
             write_row_moments(mt, d.lr_log2, row_in && l == (1 << d.lr_log2) - 1,
                               m_out + (((size_t)irow * vchunks + q.vc) * 2 + sp) * kMomQ);
         }
-        // ---- slide the window by B rows -------------------------------------------
+        // slide: the last R-1 rows of (carried ++ buffer) are carried on
 #pragma unroll
         for (int m = 0; m < R - 1; ++m) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) w[c][m] = w[c][m + B];
+            for (int c = 0; c < NC; ++c) w[c][m] = (m + B < R - 1) ? w[c][m + B] : cb_.nw[c][m + B - (R - 1)];
         }
+    };
+
+    // prologue: carried rows z0-H+1 .. z0+H-1 and the row below them, then the
+    // first chunk's loads, then the flux at z0-1/2
+    T low[NC];
+    load_row(wrap_row(z0 - H, nz), low);
+#pragma unroll
+    for (int m = 0; m < R - 1; ++m) {
+        T tmp[NC];
+        load_row(wrap_row(z0 - H + 1 + m, nz), tmp);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w[c][m] = tmp[c];
+    }
+    Buf bufA, bufB;
+    issue(z0, bufA);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        T u[R];
+        u[0] = low[c];
+#pragma unroll
+        for (int m = 1; m < R; ++m) u[m] = w[c][m - 1];
+        fprev[c] = interface_flux<SCHEME, T>(u, tv, vpos, cv, ce, weps);
+    }
+    for (int i0 = z0; i0 < zend; i0 += 2 * B) {
+        if (i0 + B < zend) issue(i0 + B, bufB);
+        compute(i0, bufA);
+        if (i0 + B >= zend) break;
+        if (i0 + 2 * B < zend) issue(i0 + 2 * B, bufA);
+        compute(i0 + B, bufB);
     }
 }
 
@@ -445,7 +464,7 @@ __device__ __forceinline__ void moments_group(const InstDesc &d, int task, int l
     const double gl = q.lane_on ? d.g[q.jl] : 0.0;
     const double agl = q.lane_on ? d.agb[q.jl] : 0.0;
     const double ca = q.sp ? -agl : gl, cb = q.sp ? agl : gl;
-    const size_t plane = (size_t)nz * nv;
+    const size_t plane = d.ps;
     const double *yb = d.y + (size_t)q.sp * 4 * plane;
     for (int i = q.z0; i < q.z0 + d.seg; ++i) {
         const bool row_in = i < q.z1;
@@ -466,17 +485,21 @@ __device__ __forceinline__ void moments_group(const InstDesc &d, int task, int l
 
 // XCD-aware block order: the hardware deals workgroups round-robin to the 8
 // XCDs; renumber so that each XCD receives a contiguous range of tasks and
-// neighbouring segments (which share halo rows) meet in the same L2.
-__device__ __forceinline__ int xcd_block(int bid, int nblk) {
+// neighbouring segments (which share halo rows) meet in the same L2.  With
+// reverse set, each XCD walks its range from the top: consecutive stages
+// alternate direction so that a stage first reads the rows its producer
+// wrote last, while they are still in the last-level cache.
+__device__ __forceinline__ int xcd_block(int bid, int nblk, bool reverse) {
     const int q = nblk >> 3, r = nblk & 7;
     const int x = bid & 7, kk = bid >> 3;
+    const int cnt = x < r ? q + 1 : q;
     const int start = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
-    return start + kk;
+    return start + (reverse ? cnt - 1 - kk : kk);
 }
 
 template <int SCHEME, int FORM, int STAGE>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void stage_kernel(InstDesc d) {
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int lb = xcd_block(blockIdx.x, gridDim.x, (STAGE & 1) != 0);
     const int wave = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & (kWave - 1);
     const int G = kWave >> d.lr_log2;
@@ -487,7 +510,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void stage_kernel(InstDesc d
 
 template <int FORM>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void moments_init_kernel(InstDesc d) {
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int lb = xcd_block(blockIdx.x, gridDim.x, false);
     const int wave = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & (kWave - 1);
     const int G = kWave >> d.lr_log2;
