@@ -83,25 +83,6 @@ double time_step(const cosenu_params &p) {
     return p.cfl * (p.L / p.nz) / vmax;
 }
 
-// eqs:perts: eps(z) = amp exp(-z^2/width), pure flavour states of |P| = 1,
-// rho_ex = eps/2 e^{i phase}, rhobar = rho^*.
-void initial_state(const cosenu_params &p, std::vector<double> &y) {
-    const size_t plane = (size_t)p.nz * p.nv;
-    y.assign(8 * plane, 0.0);
-    const double dz = p.L / p.nz, c = std::cos(p.phase), s = std::sin(p.phase);
-    for (int i = 0; i < p.nz; ++i) {
-        const double z = -0.5 * p.L + (i + 0.5) * dz;
-        const double e = p.pert_amp * std::exp(-z * z / p.pert_width);
-        const double r = std::sqrt(1.0 - e * e);
-        const double vals[8] = {0.5 * (1.0 + r), 0.5 * (1.0 - r), 0.5 * e * c, 0.5 * e * s,
-                                0.5 * (1.0 + r), 0.5 * (1.0 - r), 0.5 * e * c, -0.5 * e * s};
-        for (int cc = 0; cc < 8; ++cc) {
-            double *row = &y[cc * plane + (size_t)i * p.nv];
-            for (int j = 0; j < p.nv; ++j) row[j] = vals[cc];
-        }
-    }
-}
-
 int lr_log2_for(int nv) {
     int lr = 1, lg = 0;
     const int want = std::min(nv, kWave);
@@ -318,10 +299,9 @@ int compute_conserved(cosenu_sim *s, cosenu_conserved_t *out) {
     return COSENU_OK;
 }
 
-int upload_state(cosenu_sim *s, const double *host) {
-    const size_t row = (size_t)s->d.nz * s->d.nv * sizeof(double);
-    HIPCHK(s, hipMemcpy2DAsync(s->d.y, s->d.ps * sizeof(double), host, row, row, 8, hipMemcpyHostToDevice,
-                               s->stream));
+// After a new state is in d.y: moments of the stage-1 input and the
+// reference of the survival probabilities.
+int state_changed(cosenu_sim *s) {
     HIPCHK(s, launch_moments_init(s->d, blocks_for(s->d), s->stream));
     cosenu_conserved_t c;
     int rc = compute_conserved(s, &c);
@@ -329,6 +309,13 @@ int upload_state(cosenu_sim *s, const double *host) {
     s->ee0_nu = c.ee_nu;
     s->ee0_nubar = c.ee_nubar;
     return COSENU_OK;
+}
+
+int upload_state(cosenu_sim *s, const double *host) {
+    const size_t row = (size_t)s->d.nz * s->d.nv * sizeof(double);
+    HIPCHK(s, hipMemcpy2DAsync(s->d.y, s->d.ps * sizeof(double), host, row, row, 8, hipMemcpyHostToDevice,
+                               s->stream));
+    return state_changed(s);
 }
 
 }  // namespace
@@ -441,10 +428,10 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) {
         s->diag_part = (double *)ptr;
         s->diag_cap = cap;
     }
-    // initial data (eqs:perts)
-    std::vector<double> y0;
-    initial_state(*p, y0);
-    if ((rc = upload_state(s, y0.data()))) return fail(rc);
+    // initial data (eqs:perts), computed on the device
+    if (launch_init_state(s->d, p->L, p->pert_amp, p->pert_width, p->phase, s->stream) != hipSuccess)
+        return fail(COSENU_EDEVICE);
+    if ((rc = state_changed(s))) return fail(rc);
     if ((rc = build_graphs(s))) return fail(rc);
     *out = s;
     return COSENU_OK;

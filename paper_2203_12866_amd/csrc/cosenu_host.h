@@ -14,7 +14,6 @@ std::string validate_params(const cosenu_params &p);
 std::vector<double> bin_velocities(int nv);
 std::vector<double> gaussian_distribution(int nv, double sigma);
 double time_step(const cosenu_params &p);
-void initial_state(const cosenu_params &p, std::vector<double> &y);
 int lr_log2_for(int nv);
 int default_seg_rows(int nz, int nv);
 void set_shape(InstDesc &d, int seg);

@@ -60,14 +60,17 @@ struct WaveTask {
 // ---- launchers (stage_kernels.hip) -----------------------------------------
 hipError_t launch_stage(const InstDesc &d, int stage, int blocks, hipStream_t st);
 hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st);
+// wave_rows: every instance of the task list has nv > 32 (one row group per wave)
 hipError_t launch_batch_stage(const InstDesc *d_descs, const WaveTask *d_tasks, int nwaves, int scheme, int form,
-                              int stage, int blocks, hipStream_t st);
+                              bool wave_rows, int stage, int blocks, hipStream_t st);
 // ---- diagnostics (diag_kernels.hip) ----------------------------------------
 // per (segment, chunk) partials [nrowtasks][kDiagQ]:
 //   0..3 M0 (trace, x, y, z) summed g P - alpha gbar Pbar~ (without dz dv)
 //   4 N_nu, 5 N_nubar (sum g Tr rho, sum gbar Tr rhobar), 6 sum g |dP_nu|, 7 sum g,
 //   8 sum g rho_ee, 9 sum gbar rhobar_ee, 10 max |dP| over both species, 11 non-finite count
 hipError_t launch_diag(const InstDesc &d, double *partials, int blocks, hipStream_t st);
+// initial data of eqs:perts written into d.y
+hipError_t launch_init_state(const InstDesc &d, double L, double amp, double width, double phase, hipStream_t st);
 // per row and chunk [nz][vchunks][8]: dv sum D_q and dv sum v D_q, q = ee, xx, Re ex, Im ex
 hipError_t launch_moments_out(const InstDesc &d, double *out, int blocks, hipStream_t st);
 

@@ -4,6 +4,9 @@
 // stage kernels (row groups of lanes over v, segments of rows over z); each
 // lane accumulates its bin down the segment, then the group reduces with an
 // xor butterfly and lane 0 writes one partial per task.
+#include <algorithm>
+#include <cmath>
+
 #include "cosenu_internal.h"
 
 namespace cosenu {
@@ -117,7 +120,32 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void moments_out_kernel(Inst
     }
 }
 
+// Initial data of eqs:perts on the device: eps(z) = amp exp(-z^2/width),
+// rho_ee = (1 + sqrt(1 - eps^2))/2, rho_xx = (1 - sqrt(1 - eps^2))/2,
+// rho_ex = eps/2 e^{i phase}, rhobar = rho^*, identical in every bin.
+__global__ void init_state_kernel(InstDesc d, double L, double amp, double width, double cph, double sph) {
+    const size_t cells = (size_t)d.nz * d.nv;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t at = blockIdx.x * (size_t)blockDim.x + threadIdx.x; at < cells; at += stride) {
+        const int i = (int)(at / (size_t)d.nv);
+        const double z = -0.5 * L + (i + 0.5) * (L / d.nz);
+        const double e = amp * exp(-z * z / width);
+        const double r = sqrt(1.0 - e * e);
+        const double vals[8] = {0.5 * (1.0 + r), 0.5 * (1.0 - r), 0.5 * e * cph, 0.5 * e * sph,
+                                0.5 * (1.0 + r), 0.5 * (1.0 - r), 0.5 * e * cph, -0.5 * e * sph};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) d.y[c * d.ps + at] = vals[c];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_init_state(const InstDesc &d, double L, double amp, double width, double phase, hipStream_t st) {
+    const size_t cells = (size_t)d.nz * d.nv;
+    const int blocks = (int)std::min<size_t>((cells + 255) / 256, 65536);
+    hipLaunchKernelGGL(init_state_kernel, dim3(blocks), dim3(256), 0, st, d, L, amp, width, cos(phase), sin(phase));
+    return hipGetLastError();
+}
 
 hipError_t launch_diag(const InstDesc &d, double *partials, int blocks, hipStream_t st) {
     hipLaunchKernelGGL(diag_kernel, dim3(blocks), dim3(kWave * kWavesPerBlock), 0, st, d, partials);

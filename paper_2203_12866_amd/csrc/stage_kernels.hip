@@ -251,17 +251,20 @@ struct ChunkBuf {
 // operands of its stage combine and its moment partials) are in flight, and
 // the arithmetic reads straight from the buffer registers so that no copy
 // forces an early wait.
-template <int SCHEME, int FORM, int STAGE, int B>
+template <int SCHEME, int FORM, int STAGE, int B, bool WR>
 __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q, int l) {
     constexpr bool IN32 = FORM == 1 && STAGE == 2;  // Y3 of the FP32 form is stored in FP32
-    using T = typename std::conditional<FORM == 0, double, float>::type;
-    using TI = typename std::conditional<IN32, float, double>::type;
+    using T = typename std::conditional<FORM == 0, double, float>::type;   // stencil arithmetic
+    using TI = typename std::conditional<IN32, float, double>::type;      // stage input as stored
     constexpr int R = SCHEME == 0 ? 4 : 8;  // window rows of one interface flux
     constexpr int H = R / 2;
     constexpr int NC = 4;                   // components of one species
-    constexpr bool AUX0 = (STAGE != 0) || (FORM == 1);          // y, or acc in stage 4
-    constexpr bool AUX1 = (FORM == 1) && (STAGE == 1 || STAGE == 3);  // FP64 stage input
-    using Buf = ChunkBuf<T, B, NC, AUX0, AUX1>;
+    constexpr bool AUX0 = STAGE != 0;       // y, or acc in stage 4
+    constexpr bool AUX1 = false;
+    // The window keeps the stage input as stored; the FP32 form rounds it to
+    // FP32 where the right-hand side consumes it, and its stage combine uses
+    // the exact FP64 centre value.
+    using Buf = ChunkBuf<TI, B, NC, AUX0, AUX1>;
 
     const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
     const int sp = q.sp, z0 = q.z0, z1 = q.z1, jl = q.jl;
@@ -281,7 +284,6 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     const void *in = STAGE == 0 ? (const void *)d.y : (STAGE == 2 ? d.yb : d.ya);
     const char *inb = static_cast<const char *>(in) + (size_t)cofs * plane * sizeof(TI);
     const char *aux0b = reinterpret_cast<const char *>(STAGE == 3 ? d.acc : d.y) + (size_t)cofs * plane * 8;
-    const char *aux1b = static_cast<const char *>(d.ya) + (size_t)cofs * plane * 8;
     constexpr uint32_t out_es = (STAGE == 1 && FORM == 1) ? 4 : 8;  // element size of the stage output
     char *outb = STAGE == 0 ? static_cast<char *>(d.ya)
                : STAGE == 1 ? static_cast<char *>(d.yb)
@@ -294,17 +296,18 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     const double *m_in = STAGE == 0 ? d.mom[0] : STAGE == 1 ? d.mom[1] : STAGE == 2 ? d.mom[2] : d.mom[3];
     double *m_out = STAGE == 0 ? d.mom[1] : STAGE == 1 ? d.mom[2] : STAGE == 2 ? d.mom[3] : d.mom[0];
     const int nparts = 2 * vchunks;
-    const bool wave_row = d.lr_log2 == 6;  // one row group per wave: rows are wave-uniform
+    // WR: one row group per wave (nv > 32), so rows and their moment partials
+    // are wave-uniform and live in scalar registers
 
     const double dz_inv = d.dz_inv, dt = d.dt, hdt = 0.5 * d.dt, dt6 = d.dt * (1.0 / 6.0);
     const double third = 1.0 / 3.0;
     const double mudv = d.mudv, h3vac = d.h3vac, hexvac = d.hexvac, lam = d.lam;
     const int zend = z0 + d.seg;
 
-    auto load_row = [&](int row, T (&dst)[NC]) {
+    auto load_row = [&](int row, TI (&dst)[NC]) {
         const uint32_t off = (uint32_t)(row * nv + jl) * (uint32_t)sizeof(TI);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) dst[c] = (T)ld<TI>(inb + (size_t)c * pin, off);
+        for (int c = 0; c < NC; ++c) dst[c] = ld<TI>(inb + (size_t)c * pin, off);
     };
 
     // issue every load of the chunk starting at row i0
@@ -312,7 +315,7 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             int irow = min(i0 + b, nz - 1);
-            if (wave_row) irow = __builtin_amdgcn_readfirstlane(irow);
+            if constexpr (WR) irow = __builtin_amdgcn_readfirstlane(irow);
             const double *mp = m_in + (size_t)irow * nparts * kMomQ;
 #pragma unroll
             for (int k = 0; k < kMomQ; ++k) cb_.S[b][k] = mp[k] + mp[kMomQ + k];
@@ -326,7 +329,7 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
             // rows past a ragged segment end are not produced; their look-ahead
             // stays on the last produced row (always inside [0, 2 nz))
             const int ahead = min(i0 + b + H, z1 - 1 + H);
-            T tmp[NC];
+            TI tmp[NC];
             load_row(wrap_row(ahead, nz), tmp);
 #pragma unroll
             for (int c = 0; c < NC; ++c) cb_.nw[c][b] = tmp[c];
@@ -337,13 +340,12 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 if constexpr (AUX0) cb_.a0[b][c] = ld<double>(aux0b + (size_t)c * p64, off);
-                if constexpr (AUX1) cb_.a1[b][c] = ld<double>(aux1b + (size_t)c * p64, off);
             }
         }
     };
 
-    T w[NC][R - 1];  // carried window rows i0-H+1 .. i0+H-1
-    T fprev[NC];     // flux at i0-1/2
+    TI w[NC][R - 1];  // carried window rows i0-H+1 .. i0+H-1
+    T fprev[NC];      // flux at i0-1/2
 
     // the B rows of a chunk: window row m of row i0+b is w (m < R-1-b) or the buffer
     auto compute = [&](int i0, const Buf &cb_) {
@@ -352,8 +354,8 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
             const int i = i0 + b;
             const bool row_in = i < z1;
             const int irow = min(i, nz - 1);
-            auto win = [&](int c, int m) -> T {  // window row i-H+1+m
-                const int k = b + m;             // index in carried ++ buffer
+            auto win = [&](int c, int m) -> TI {  // window row i-H+1+m, as stored
+                const int k = b + m;              // index in carried ++ buffer
                 return k < R - 1 ? w[c][k] : cb_.nw[c][k - (R - 1)];
             };
             const double A0 = cb_.S[b][0] - v * cb_.S[b][3];
@@ -362,15 +364,15 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
             const double h3 = h3vac + sgn * (lam + mudv * A0);
             const double hr = hexvac + sgn * (mudv * A1);
             const double hi = mudv * A2;
-            double u[NC], kk[NC];
+            double u[NC], kk[NC];  // centre values as the right-hand side sees them
 #pragma unroll
-            for (int c = 0; c < NC; ++c) u[c] = (double)win(c, H - 1);
+            for (int c = 0; c < NC; ++c) u[c] = (double)(T)win(c, H - 1);
             minus_i_commutator(h3, hr, hi, u[0], u[1], u[2], u[3], kk[0], kk[1], kk[2], kk[3]);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 T uu[R];
 #pragma unroll
-                for (int m = 0; m < R; ++m) uu[m] = win(c, m);
+                for (int m = 0; m < R; ++m) uu[m] = (T)win(c, m);
                 const T fnew = interface_flux<SCHEME, T>(uu, tv, vpos, cv, ce, weps);
                 kk[c] -= ((double)fnew - (double)fprev[c]) * dz_inv;
                 fprev[c] = fnew;
@@ -381,21 +383,17 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
             const bool on = row_in && q.lane_on;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
+                const double centre = (double)win(c, H - 1);  // exact stage input (FP64 except Y3)
                 if constexpr (STAGE == 0) {
-                    if constexpr (FORM == 0) o[c] = u[c] + hdt * kk[c];
-                    else o[c] = cb_.a0[b][c] + hdt * kk[c];
+                    o[c] = centre + hdt * kk[c];
                 } else if constexpr (STAGE == 1) {
-                    double y2;
-                    if constexpr (FORM == 0) y2 = u[c];
-                    else y2 = cb_.a1[b][c];
+                    const double y2 = centre;
                     o[c] = cb_.a0[b][c] + hdt * kk[c];
                     if (on) st<double>(accw + (size_t)c * p64, off64, ((cb_.a0[b][c] + y2) + dt * kk[c]) * third);
                 } else if constexpr (STAGE == 2) {
                     o[c] = cb_.a0[b][c] + dt * kk[c];
                 } else {
-                    double y4;
-                    if constexpr (FORM == 0) y4 = u[c];
-                    else y4 = cb_.a1[b][c];
+                    const double y4 = centre;
                     o[c] = (cb_.a0[b][c] + y4 * third) + dt6 * kk[c];
                 }
                 if (on) {
@@ -420,11 +418,11 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
 
     // prologue: carried rows z0-H+1 .. z0+H-1 and the row below them, then the
     // first chunk's loads, then the flux at z0-1/2
-    T low[NC];
+    TI low[NC];
     load_row(wrap_row(z0 - H, nz), low);
 #pragma unroll
     for (int m = 0; m < R - 1; ++m) {
-        T tmp[NC];
+        TI tmp[NC];
         load_row(wrap_row(z0 - H + 1 + m, nz), tmp);
 #pragma unroll
         for (int c = 0; c < NC; ++c) w[c][m] = tmp[c];
@@ -434,9 +432,9 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         T u[R];
-        u[0] = low[c];
+        u[0] = (T)low[c];
 #pragma unroll
-        for (int m = 1; m < R; ++m) u[m] = w[c][m - 1];
+        for (int m = 1; m < R; ++m) u[m] = (T)w[c][m - 1];
         fprev[c] = interface_flux<SCHEME, T>(u, tv, vpos, cv, ce, weps);
     }
     for (int i0 = z0; i0 < zend; i0 += 2 * B) {
@@ -448,10 +446,10 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     }
 }
 
-template <int SCHEME, int FORM, int STAGE>
+template <int SCHEME, int FORM, int STAGE, bool WR>
 __device__ __forceinline__ void stage_group(const InstDesc &d, int task, int l) {
     const GroupGeom q = group_geom(d, task, l);
-    stage_body<SCHEME, FORM, STAGE, kChunkRows[SCHEME]>(d, q, l);
+    stage_body<SCHEME, FORM, STAGE, kChunkRows[SCHEME], WR>(d, q, l);
 }
 
 // Moment partials of the stage-1 input (the state y) for a freshly set state,
@@ -497,7 +495,7 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk, bool reverse) {
     return start + (reverse ? cnt - 1 - kk : kk);
 }
 
-template <int SCHEME, int FORM, int STAGE>
+template <int SCHEME, int FORM, int STAGE, bool WR>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void stage_kernel(InstDesc d) {
     const int lb = xcd_block(blockIdx.x, gridDim.x, (STAGE & 1) != 0);
     const int wave = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
@@ -505,7 +503,8 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void stage_kernel(InstDesc d
     const int G = kWave >> d.lr_log2;
     const int task = wave * G + (lane >> d.lr_log2);
     if (wave * G >= d.ntasks) return;  // whole wave idle (uniform)
-    stage_group<SCHEME, FORM, STAGE>(d, task, lane & ((1 << d.lr_log2) - 1));
+    if constexpr (WR) stage_group<SCHEME, FORM, STAGE, true>(d, wave, lane);
+    else stage_group<SCHEME, FORM, STAGE, false>(d, task, lane & ((1 << d.lr_log2) - 1));
 }
 
 template <int FORM>
@@ -523,7 +522,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void moments_init_kernel(Ins
 // (the list is sorted by decreasing cost on the host).  Every wave reads its
 // instance descriptor, then runs the same group code as a single instance.
 // One kernel per scheme, so each gets its own register budget.
-template <int SCHEME, int FORM, int STAGE>
+template <int SCHEME, int FORM, int STAGE, bool WR>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void batch_stage_kernel(const InstDesc *__restrict__ descs,
                                                                            const WaveTask *__restrict__ tasks,
                                                                            int nwt) {
@@ -533,7 +532,8 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void batch_stage_kernel(cons
     for (int wt = first; wt < nwt; wt += nwaves) {
         const WaveTask t = tasks[wt];
         const InstDesc &d = descs[t.inst];
-        stage_group<SCHEME, FORM, STAGE>(d, t.task0 + (lane >> d.lr_log2), lane & ((1 << d.lr_log2) - 1));
+        if constexpr (WR) stage_group<SCHEME, FORM, STAGE, true>(d, t.task0, lane);
+        else stage_group<SCHEME, FORM, STAGE, false>(d, t.task0 + (lane >> d.lr_log2), lane & ((1 << d.lr_log2) - 1));
     }
 }
 
@@ -554,34 +554,48 @@ int row_blocks_for(const InstDesc &d) {
 }
 
 namespace {
-template <int SCHEME, int FORM>
+template <int SCHEME, int FORM, bool WR>
 hipError_t launch_stage_t(const InstDesc &d, int stage, dim3 grid, dim3 block, hipStream_t st) {
     switch (stage) {
-        case 0: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 0>), grid, block, 0, st, d); break;
-        case 1: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 1>), grid, block, 0, st, d); break;
-        case 2: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 2>), grid, block, 0, st, d); break;
-        default: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 3>), grid, block, 0, st, d); break;
+        case 0: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 0, WR>), grid, block, 0, st, d); break;
+        case 1: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 1, WR>), grid, block, 0, st, d); break;
+        case 2: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 2, WR>), grid, block, 0, st, d); break;
+        default: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 3, WR>), grid, block, 0, st, d); break;
     }
     return hipGetLastError();
 }
-template <int SCHEME, int FORM>
+template <int SCHEME, int FORM, bool WR>
 hipError_t launch_batch_t(const InstDesc *dd, const WaveTask *tk, int nwt, int stage, dim3 grid, dim3 block,
                           hipStream_t st) {
     switch (stage) {
-        case 0: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 0>), grid, block, 0, st, dd, tk, nwt); break;
-        case 1: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 1>), grid, block, 0, st, dd, tk, nwt); break;
-        case 2: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 2>), grid, block, 0, st, dd, tk, nwt); break;
-        default: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 3>), grid, block, 0, st, dd, tk, nwt); break;
+        case 0: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 0, WR>), grid, block, 0, st, dd, tk, nwt); break;
+        case 1: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 1, WR>), grid, block, 0, st, dd, tk, nwt); break;
+        case 2: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 2, WR>), grid, block, 0, st, dd, tk, nwt); break;
+        default: hipLaunchKernelGGL((batch_stage_kernel<SCHEME, FORM, 3, WR>), grid, block, 0, st, dd, tk, nwt); break;
     }
     return hipGetLastError();
+}
+template <bool WR>
+hipError_t launch_stage_w(const InstDesc &d, int stage, dim3 grid, dim3 block, hipStream_t st) {
+    if (d.scheme == 0) return d.form == 0 ? launch_stage_t<0, 0, WR>(d, stage, grid, block, st)
+                                          : launch_stage_t<0, 1, WR>(d, stage, grid, block, st);
+    return d.form == 0 ? launch_stage_t<1, 0, WR>(d, stage, grid, block, st)
+                       : launch_stage_t<1, 1, WR>(d, stage, grid, block, st);
+}
+template <bool WR>
+hipError_t launch_batch_w(const InstDesc *dd, const WaveTask *tk, int nwt, int scheme, int form, int stage, dim3 grid,
+                          dim3 block, hipStream_t st) {
+    if (scheme == 0) return form == 0 ? launch_batch_t<0, 0, WR>(dd, tk, nwt, stage, grid, block, st)
+                                      : launch_batch_t<0, 1, WR>(dd, tk, nwt, stage, grid, block, st);
+    return form == 0 ? launch_batch_t<1, 0, WR>(dd, tk, nwt, stage, grid, block, st)
+                     : launch_batch_t<1, 1, WR>(dd, tk, nwt, stage, grid, block, st);
 }
 }  // namespace
 
 hipError_t launch_stage(const InstDesc &d, int stage, int blocks, hipStream_t st) {
     const dim3 grid(blocks), block(kWave * kWavesPerBlock);
-    if (d.scheme == 0) return d.form == 0 ? launch_stage_t<0, 0>(d, stage, grid, block, st)
-                                          : launch_stage_t<0, 1>(d, stage, grid, block, st);
-    return d.form == 0 ? launch_stage_t<1, 0>(d, stage, grid, block, st) : launch_stage_t<1, 1>(d, stage, grid, block, st);
+    return d.lr_log2 == 6 ? launch_stage_w<true>(d, stage, grid, block, st)
+                          : launch_stage_w<false>(d, stage, grid, block, st);
 }
 
 hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st) {
@@ -592,12 +606,10 @@ hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st) {
 }
 
 hipError_t launch_batch_stage(const InstDesc *d_descs, const WaveTask *d_tasks, int nwt, int scheme, int form,
-                              int stage, int blocks, hipStream_t st) {
+                              bool wave_rows, int stage, int blocks, hipStream_t st) {
     const dim3 grid(blocks), block(kWave * kWavesPerBlock);
-    if (scheme == 0) return form == 0 ? launch_batch_t<0, 0>(d_descs, d_tasks, nwt, stage, grid, block, st)
-                                      : launch_batch_t<0, 1>(d_descs, d_tasks, nwt, stage, grid, block, st);
-    return form == 0 ? launch_batch_t<1, 0>(d_descs, d_tasks, nwt, stage, grid, block, st)
-                     : launch_batch_t<1, 1>(d_descs, d_tasks, nwt, stage, grid, block, st);
+    return wave_rows ? launch_batch_w<true>(d_descs, d_tasks, nwt, scheme, form, stage, grid, block, st)
+                     : launch_batch_w<false>(d_descs, d_tasks, nwt, scheme, form, stage, grid, block, st);
 }
 
 }  // namespace cosenu

@@ -1,0 +1,68 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times (autotuned segment length).
+
+* FD + KO, 16384 x 128: after 150 GPU steps from the initial data, one more
+  GPU step is compared with one oracle step from the same (downloaded)
+  state, over the whole grid.
+* FV WENO7, 65536 x 256 (omega = 1e-3): one step of the oracle on periodic
+  z-slabs cut from the GPU state with a 16-row margin (4 stages x 4 rows of
+  WENO7 halo) is compared with the GPU step on the slab interiors, at the
+  perturbation, at the periodic seam and at a random place.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+from paper_2203_12866_amd import cosenu
+from paper_2203_12866_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _one_step_pair(w, warm_steps):
+    with cosenu.Sim(w) as s:
+        s.autotune()
+        s.step(warm_steps)
+        y0 = s.get_state()
+        s.step(1)
+        y1 = s.get_state()
+        dt = s.info()["dt"]
+    return y0, y1, dt
+
+
+@pytest.mark.parametrize("prec", [wl.FP64, wl.FP32_ACC64])
+def test_fd_16384x128_one_step_full_grid(prec):
+    w = wl.fd_16384x128(2, prec)
+    y0, y1, dt = _one_step_pair(w, 150)
+    p = o.problem_from_workload(w)
+    assert abs(p.dt - dt) < 1e-15
+    ref = o.rk4(p, y0, 1)
+    err = np.abs(y1 - ref)
+    print(f"precision {prec}: max abs {err.max():.3e}")
+    if prec == wl.FP64:
+        assert err.max() <= 1e-12
+    else:
+        # FP32 stencils on FP32-rounded stage values: one step moves every value by
+        # at most ~dt * |k| with k rounded at ~6e-8 relative
+        assert err.max() <= 1e-7
+    assert np.abs(ref[2:4] - y0[2:4]).max() > 0  # the perturbation moved
+
+
+@pytest.mark.parametrize("prec", [wl.FP64, wl.FP32_ACC64])
+def test_fv_65536x256_windows(prec):
+    w = wl.fv_65536x256(3, prec)
+    nz, nv = w["nz"], w["nv"]
+    y0, y1, dt = _one_step_pair(w, 40)
+    margin, width = 16, 48
+    rng = np.random.default_rng(0)
+    starts = [nz // 2 - width // 2, 0, int(rng.integers(0, nz))]
+    for a in starts:
+        rows = np.arange(a - margin, a + width + margin) % nz
+        slab = np.ascontiguousarray(y0[:, rows, :])
+        p = o.problem_from_workload(dict(w, nz=len(rows), L=len(rows) * (w["L"] / nz)))
+        p.dt = dt
+        ref = o.rk4(p, slab, 1)[:, margin:margin + width, :]
+        got = y1[:, rows[margin:margin + width], :]
+        err = np.abs(got - ref).max()
+        print(f"precision {prec}, window at {a}: max abs {err:.3e}")
+        assert err <= (1e-12 if prec == wl.FP64 else 1e-7), (a, err)
