@@ -74,11 +74,14 @@ def run_form(cosenu, torch, w, steps, warmup, seg, stage_steps):
     state = sim.get_state()
     sim.close()
     cells = w["nz"] * w["nv"]
-    launch_s = sum(stage_ms) / (4.0 * stage_steps) / 1e3
+    # average stage-launch duration over the timed region: HIP events on the
+    # sim's stream around the K graph launches (4 stage launches per step)
+    launch_s = ev_ms / (4.0 * steps) / 1e3
     return dict(seg=chosen, wall=wall, ev_ms=ev_ms, stage_ms=stage_ms, info=info, state=state,
                 updates=cells * 4.0 * steps / wall,
                 gbps_model=info["bytes_per_step"] * steps / wall / 1e9,
                 launch_s=launch_s,
+                stage_us=[m * 1e3 / stage_steps for m in stage_ms],
                 achieved_gbps=info["bytes_per_step"] / 4.0 / launch_s / 1e9)
 
 
@@ -122,7 +125,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="fd_ko_16384x128", choices=sorted(WORKLOADS))
     ap.add_argument("--seg-rows", type=int, default=None, help="fixed launch shape (default: autotune)")
-    ap.add_argument("--stage-steps", type=int, default=50, help="steps timed launch by launch for the roofline")
+    ap.add_argument("--stage-steps", type=int, default=50, help="steps timed launch by launch (eager, per-stage breakdown)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     args = ap.parse_args()
@@ -180,6 +183,7 @@ def main():
             "traffic": measured_traffic(args.workload, "fp32acc"),
             "kernel": "stage_kernel<FD,FP32acc>" if w["scheme"] == 0 else "stage_kernel<WENO7,FP32acc>",
             "avg_launch_us": head["launch_s"] * 1e6,
+            "stage_us_eager": head["stage_us"],
         },
         "fp64_form": {
             "value": res["fp64"]["updates"],
@@ -189,6 +193,7 @@ def main():
             "roofline_achieved_gbps": res["fp64"]["achieved_gbps"],
             "roofline_frac": res["fp64"]["achieved_gbps"] / PEAK_HBM_GBPS,
             "avg_launch_us": res["fp64"]["launch_s"] * 1e6,
+            "stage_us_eager": res["fp64"]["stage_us"],
             "seg_rows": res["fp64"]["seg"],
         },
         "fp32_speedup_over_fp64": head["updates"] / res["fp64"]["updates"],

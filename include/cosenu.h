@@ -64,7 +64,8 @@ typedef struct cosenu_batch cosenu_batch;
 
 /* Problem description (Sec. 2, 3 and 5).  Units: 1/mu for t and z.
  *  nz, nv      number of z cells (periodic) and velocity bins; nz >= 5 for FD,
- *              nz >= 9 for WENO7; nv >= 1.  Bins are midpoints
+ *              nz >= 9 for WENO7; nv >= 2 (one bin would have max|v| = 0);
+ *              nz * nv <= 2^29 (per-plane byte offsets are 32 bits).  Bins are midpoints
  *              v_j = -1 + (j + 1/2) * 2/nv; the velocity integral of eq:ham is
  *              the Riemann sum over them (Sec. 3).
  *  L           domain length; cells are centred at z_i = -L/2 + (i + 1/2) L/nz.
