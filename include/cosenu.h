@@ -154,6 +154,12 @@ int cosenu_sync(cosenu_sim *s);
  * of the survival probabilities; t and step are left unchanged. */
 int cosenu_get_state(cosenu_sim *s, double *out, size_t n);
 int cosenu_set_state(cosenu_sim *s, const double *in, size_t n);
+/* Copies the FP64 state of nrows consecutive z rows starting at row z0 to the
+ * host, as [8][nrows][nv]; rows wrap periodically (z0 may be any integer,
+ * 1 <= nrows <= nz).  n is the number of doubles in the caller's buffer (must
+ * be >= 8*nrows*nv).  Synchronises the handle's stream.  Meant for checking
+ * and inspecting a slab of a grid too large to download whole. */
+int cosenu_get_rows(cosenu_sim *s, int64_t z0, int32_t nrows, double *out, size_t n);
 /* Sets the simulation clock (used with set_state to resume a checkpoint). */
 int cosenu_set_clock(cosenu_sim *s, double t, int64_t step);
 

@@ -501,3 +501,14 @@ int oracle_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Sets the OpenMP thread count of later calls (n >= 1); returns the count now in force. */
+int oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

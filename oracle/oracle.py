@@ -88,6 +88,8 @@ def lib():
         L.oracle_diagnostics.argtypes = [ctypes.POINTER(_Params), dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
+        L.oracle_set_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -205,6 +207,11 @@ def diagnostics(p: Problem, y: np.ndarray) -> dict:
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> int:
+    """Thread count of later oracle calls; returns the count in force."""
+    return lib().oracle_set_num_threads(int(n))
 
 
 def problem_from_workload(w: dict) -> Problem:

@@ -102,6 +102,7 @@ def _lib():
             "cosenu_sync": (ctypes.c_int, [vp]),
             "cosenu_get_state": (ctypes.c_int, [vp, dp, sz]),
             "cosenu_set_state": (ctypes.c_int, [vp, dp, sz]),
+            "cosenu_get_rows": (ctypes.c_int, [vp, ctypes.c_int64, ctypes.c_int32, dp, sz]),
             "cosenu_set_clock": (ctypes.c_int, [vp, ctypes.c_double, i64]),
             "cosenu_moments": (ctypes.c_int, [vp, dp, sz]),
             "cosenu_conserved": (ctypes.c_int, [vp, ctypes.POINTER(Conserved)]),
@@ -209,6 +210,12 @@ class Sim:
     def get_state(self) -> np.ndarray:
         out = np.empty((8, self.nz, self.nv))
         self._check(_lib().cosenu_get_state(self._h, _dptr(out), out.size), "cosenu_get_state")
+        return out
+
+    def get_rows(self, z0: int, nrows: int) -> np.ndarray:
+        """State of rows z0 .. z0+nrows-1 (periodic), shape (8, nrows, nv)."""
+        out = np.empty((8, int(nrows), self.nv))
+        self._check(_lib().cosenu_get_rows(self._h, int(z0), int(nrows), _dptr(out), out.size), "cosenu_get_rows")
         return out
 
     def set_state(self, y: np.ndarray):

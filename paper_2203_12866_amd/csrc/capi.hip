@@ -469,6 +469,23 @@ int cosenu_get_state(cosenu_sim *s, double *out, size_t n) {
     return COSENU_OK;
 }
 
+int cosenu_get_rows(cosenu_sim *s, int64_t z0, int32_t nrows, double *out, size_t n) {
+    SIM_CHECK(s);
+    const int nz = s->d.nz, nv = s->d.nv;
+    if (!out || nrows < 1 || nrows > nz || n < (size_t)8 * nrows * nv) return COSENU_EINVAL;
+    const int first = (int)(((z0 % nz) + nz) % nz);
+    const int n1 = std::min(nrows, nz - first);  // rows before the periodic seam
+    const size_t rowb = (size_t)nv * sizeof(double);
+    const size_t dpitch = (size_t)nrows * rowb, spitch = s->d.ps * sizeof(double);
+    HIPCHK(s, hipMemcpy2DAsync(out, dpitch, s->d.y + (size_t)first * nv, spitch, (size_t)n1 * rowb, 8,
+                               hipMemcpyDeviceToHost, s->stream));
+    if (n1 < nrows)
+        HIPCHK(s, hipMemcpy2DAsync(out + (size_t)n1 * nv, dpitch, s->d.y, spitch, (size_t)(nrows - n1) * rowb, 8,
+                                   hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return COSENU_OK;
+}
+
 int cosenu_set_state(cosenu_sim *s, const double *in, size_t n) {
     SIM_CHECK(s);
     const size_t need = (size_t)8 * s->d.nz * s->d.nv;

@@ -12,10 +12,11 @@ constexpr int kWave = 64;           // CDNA wavefront width
 constexpr int kWavesPerBlock = 4;   // stage kernels run 256-thread workgroups
 constexpr int kMomQ = 6;            // reduced quantities per row and part:
                                     //   sum D3, sum ReDex, sum ImDex, and the same times v
-constexpr int kDiagQ = 12;
-constexpr int kChunkRows[2] = {1, 1};  // rows per load chunk of the stage kernels: FD, WENO7
-constexpr int kPlanePad = 544;         // elements between planes beyond nz*nv (4352 B in FP64, 2176 B
-                                       // in FP32: 128-byte aligned, off the power-of-two strides)          // per-task partials of the conserved-quantity kernel
+constexpr int kDiagQ = 12;         // per-task partials of the conserved-quantity kernel
+constexpr int kPlanePad = 544;      // elements between planes beyond nz*nv (4352 B in FP64, 2176 B
+                                    // in FP32: 128-byte aligned, off the power-of-two strides)
+constexpr int kLdsQStride = 68;     // doubles between quantity rows of a wave's moment scratch
+constexpr int kLdsPerWave = 8 * kLdsQStride;  // LDS doubles per wave (6 quantities + 2 pad rows)
 
 // Everything one stage launch needs about one simulation.  Passed by value to
 // the single-instance kernels and stored in device memory for the batch.

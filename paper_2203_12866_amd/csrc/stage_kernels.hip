@@ -41,6 +41,13 @@
 namespace cosenu {
 namespace {
 
+// Global-address-space views.  Pointers read from a descriptor in memory (the
+// batch kernels) are otherwise generic, and generic (flat) loads also count
+// against the LDS wait counter, which would tie the row prefetch to the LDS
+// moment reduction.
+using gchar = __attribute__((address_space(1))) char;
+using gdouble = __attribute__((address_space(1))) double;
+
 __device__ __forceinline__ int wrap_row(int r, int nz) { return r < 0 ? r + nz : (r >= nz ? r - nz : r); }
 
 // Cross-lane move of an FP64 value with a fixed DPP pattern (two 32-bit
@@ -84,7 +91,9 @@ __device__ __forceinline__ T fd_ko_flux(T um1, T u0, T up1, T up2, T cv, T ce) {
 template <typename T>
 __device__ __forceinline__ T weno_combine(T s0, T s1, T s2, T s3, T q0, T q1, T q2, T q3);
 
-// FP64: one division, by multiplying every weight by s0 s1 s2 s3.
+// FP64: every weight is multiplied by s0 s1 s2 s3, which leaves one quotient.
+// It is formed from the hardware reciprocal refined by one Newton step and one
+// residual correction: within a few ulp, with no correctly rounded division.
 template <>
 __device__ __forceinline__ double weno_combine<double>(double s0, double s1, double s2, double s3, double q0,
                                                        double q1, double q2, double q3) {
@@ -95,7 +104,10 @@ __device__ __forceinline__ double weno_combine<double>(double s0, double s1, dou
     const double e3 = p01 * s2;
     const double num = (e0 * q0 + e1 * q1) + (e2 * q2 + e3 * q3);
     const double den = (e0 + e1) + (e2 + e3);
-    return num / den;
+    double r = __builtin_amdgcn_rcp(den);
+    r = __builtin_fma(__builtin_fma(-den, r, 1.0), r, r);
+    const double x = num * r;
+    return __builtin_fma(__builtin_fma(-den, x, num), r, x);
 }
 
 // FP32: hardware reciprocals (the products of three s_r could leave FP32 range).
@@ -154,13 +166,48 @@ __device__ __forceinline__ void minus_i_commutator(double h3, double hr, double 
 
 // Reduce the per-lane integrands over the group; the writer is the group's
 // last lane, which holds the totals.
-__device__ __forceinline__ void write_row_moments(double m[kMomQ], int lr_log2, bool writer, double *dst) {
+__device__ __forceinline__ void write_row_moments(double m[kMomQ], int lr_log2, bool writer, gdouble *dst) {
 #pragma unroll
     for (int q = 0; q < kMomQ; ++q) m[q] = group_sum(m[q], lr_log2);
     if (writer) {
 #pragma unroll
         for (int q = 0; q < kMomQ; ++q) dst[q] = m[q];
     }
+}
+
+// Row totals of the six integrands over the 64 lanes of a wave (one row group
+// per wave) through the wave's LDS scratch: every lane stores its six values;
+// lane 8q + p adds the eight values of quantity q held by lanes 8p .. 8p+7;
+// three DPP steps combine the eight partial sums of q (every lane of the
+// eight ends with the same total) and lane 8q writes it.  The association
+// order is fixed.  LDS operations of one wave complete in program order, so
+// the only ordering needed is the compiler's (signal fences).
+__device__ __forceinline__ void wave_row_moments(const double m[kMomQ], double *lds, int lane, gdouble *dst) {
+#pragma unroll
+    for (int q = 0; q < kMomQ; ++q) lds[q * kLdsQStride + lane] = m[q];
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const int qq = lane >> 3, part = lane & 7;
+    const double2 *src = reinterpret_cast<const double2 *>(lds + qq * kLdsQStride + part * 8);
+    const double2 x0 = src[0], x1 = src[1], x2 = src[2], x3 = src[3];
+    double s = ((x0.x + x0.y) + (x1.x + x1.y)) + ((x2.x + x2.y) + (x3.x + x3.y));
+    s += dpp_f64<0xB1, 0xF>(s);   // quad_perm [1,0,3,2]
+    s += dpp_f64<0x4E, 0xF>(s);   // quad_perm [2,3,0,1]
+    s += dpp_f64<0x141, 0xF>(s);  // row_half_mirror
+    if (part == 0 && qq < kMomQ) dst[qq] = s;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// A register copy the compiler cannot coalesce with its source (the output
+// operand is early-clobber, so it gets a register of its own).
+__device__ __forceinline__ double fresh_copy(double x) {
+    double y;
+    asm("v_mov_b64 %0, %1" : "=&v"(y) : "v"(x));
+    return y;
+}
+__device__ __forceinline__ float fresh_copy(float x) {
+    float y;
+    asm("v_mov_b32 %0, %1" : "=&v"(y) : "v"(x));
+    return y;
 }
 
 template <typename T>
@@ -173,12 +220,12 @@ __device__ __forceinline__ T load_as(const void *base, size_t idx, bool f32) {
 // is 32 bits (planes are limited to 2^29 cells), so the address is formed by
 // the memory unit from a scalar base plus one VGPR.
 template <typename T>
-__device__ __forceinline__ T ld(const char *base, uint32_t off) {
-    return *reinterpret_cast<const T *>(base + off);
+__device__ __forceinline__ T ld(const gchar *base, uint32_t off) {
+    return *reinterpret_cast<const __attribute__((address_space(1))) T *>(base + off);
 }
 template <typename T>
-__device__ __forceinline__ void st(char *base, uint32_t off, T v) {
-    *reinterpret_cast<T *>(base + off) = v;
+__device__ __forceinline__ void st(gchar *base, uint32_t off, T v) {
+    *reinterpret_cast<__attribute__((address_space(1))) T *>(base + off) = v;
 }
 
 // Moment integrands of one species' four components for one bin: the
@@ -198,17 +245,27 @@ __device__ __forceinline__ void species_moment_terms(const double o[4], double c
     m[5] = v * d2;
 }
 
-// Interface flux from the R window rows around it (FD: rows i-1..i+2, WENO7:
-// rows i-3..i+4); the upwind side of WENO7 follows the sign of v.
-template <int SCHEME, typename T>
-__device__ __forceinline__ T interface_flux(const T (&u)[SCHEME == 0 ? 4 : 8], T tv, bool vpos, T cv, T ce, T weps) {
+// Interface flux from the R window rows around it (FD: rows i-1..i+2 of the
+// interface i+1/2, WENO7: rows i-3..i+4), in window order.
+// WENO7 reconstructs f = v u.  Scaling eps by 1/v^2 makes it homogeneous of
+// degree one in f, WENO7(v u; eps) = v WENO7(u; eps / v^2), so the products
+// v u drop out (epsv is eps / v^2, or eps for v = 0, where the flux is 0).
+// The upwind side follows the sign of v (Appendix A; v < 0 takes the stencil
+// mirrored about the interface).  With MIX the lanes of a wave may upwind to
+// either side and select per lane; otherwise the wave marches in its upwind
+// direction, its window is already in upwind order, and nothing is selected.
+// The window rows are scalar arguments (FD uses u0..u3): selecting between
+// elements of an array would be lowered to an indexed read.
+template <int SCHEME, bool MIX, typename T>
+__device__ __forceinline__ T interface_flux(T u0, T u1, T u2, T u3, T u4, T u5, T u6, T u7, T tv, bool vpos, T cv,
+                                            T ce, T epsv) {
     if constexpr (SCHEME == 0) {
-        return fd_ko_flux<T>(u[0], u[1], u[2], u[3], cv, ce);
+        return fd_ko_flux<T>(u0, u1, u2, u3, cv, ce);
+    } else if constexpr (MIX) {
+        return tv * weno7_flux<T>(vpos ? u0 : u7, vpos ? u1 : u6, vpos ? u2 : u5, vpos ? u3 : u4, vpos ? u4 : u3,
+                                  vpos ? u5 : u2, vpos ? u6 : u1, epsv);
     } else {
-        T a[7];
-#pragma unroll
-        for (int q = 0; q < 7; ++q) a[q] = tv * (vpos ? u[q] : u[7 - q]);
-        return weno7_flux<T>(a[0], a[1], a[2], a[3], a[4], a[5], a[6], weps);
+        return tv * weno7_flux<T>(u0, u1, u2, u3, u4, u5, u6, epsv);
     }
 }
 
@@ -236,38 +293,74 @@ __device__ __forceinline__ GroupGeom group_geom(const InstDesc &d, int task, int
     return q;
 }
 
-// Everything one chunk of B rows needs from memory, loaded ahead of use.
-template <typename T, int B, int NC, bool AUX0, bool AUX1>
-struct ChunkBuf {
-    T nw[NC][B];           // the B window rows entering with this chunk
-    double a0[B][NC];      // y (or acc in stage 4) of the B produced rows
-    double a1[B][NC];      // the FP64 stage input of the B rows (FP32 form, stages 2 and 4)
-    double S[B][kMomQ];    // summed moment partials of the B input rows
+// Everything one row needs from memory, loaded one row ahead of its use.
+template <typename TI, int NC>
+struct RowBuf {
+    TI nw[NC];        // the window row entering with this row (the look-ahead row)
+    double a0[NC];    // y (or acc in stage 4) of the produced row
+    double S[kMomQ];  // summed moment partials of the input row
+    double pv[2];     // or, with one row group per wave, its lane's two partials
 };
 
-// One row group of one species: march down the segment in chunks of B rows,
-// software-pipelined one chunk deep.  Two chunk buffers alternate: while
-// chunk c is computed, the loads of chunk c+1 (its new window rows, the FP64
-// operands of its stage combine and its moment partials) are in flight, and
-// the arithmetic reads straight from the buffer registers so that no copy
-// forces an early wait.
-template <int SCHEME, int FORM, int STAGE, int B, bool WR>
-__device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q, int l) {
+// The moment partials of an input row come from nparts = 2 vchunks producer
+// groups.  With one row group per wave and nparts <= 16 they are read
+// lane-distributed: lane 16 g + p holds part p of quantities g and g + 3 (zero
+// past the parts), one load per lane and quantity pair, and are summed only
+// where they are used, so that their load never forces an early wait on the
+// loads issued after it.  A DPP sum over the 16 lanes of each g (p in pairs,
+// then pairs of pairs; a fixed order) leaves every lane of the group with the
+// totals, which are then read as wave-uniform values.
+constexpr int kPartLanes = 16;
+
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ void sum_row_parts(const double pv[2], int plog, double S[kMomQ]) {
+    const double t0 = group_sum(pv[0], plog), t1 = group_sum(pv[1], plog);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        S[g] = readlane_f64(t0, kPartLanes * g);
+        S[g + 3] = readlane_f64(t1, kPartLanes * g);
+    }
+}
+
+// One row group of one species marches through its segment, one row per step,
+// software-pipelined one row deep: while row k is computed, the loads of row
+// k+1 (its look-ahead window row, the FP64 operand of its stage combine and its
+// moment partials) are in flight; two buffers alternate so that the arithmetic
+// reads straight from the buffer registers and no copy forces an early wait.
+// Step k handles row start + dir k.  dir = +1 marches up z from z0; dir = -1
+// (WENO7 waves whose bins all have v < 0) marches down from z1 - 1, with the
+// window mirrored so that it is in upwind order; the flux then produced at each
+// step is the one on the lower face, hence the sign of dzs.
+template <int SCHEME, int FORM, int STAGE, bool WR, bool MIX, bool REV>
+__device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q, int l, int dir, double *lds) {
     constexpr bool IN32 = FORM == 1 && STAGE == 2;  // Y3 of the FP32 form is stored in FP32
     using T = typename std::conditional<FORM == 0, double, float>::type;   // stencil arithmetic
     using TI = typename std::conditional<IN32, float, double>::type;      // stage input as stored
-    constexpr int R = SCHEME == 0 ? 4 : 8;  // window rows of one interface flux
-    constexpr int H = R / 2;
+    // Window: R rows around the current one, slot m holding row r + dir (m - CTR).
+    // FD needs rows i-1..i+2 of the face i+1/2.  WENO7 needs rows i-3..i+3 of
+    // the upwind-ordered stencil; with MIX a lane may need the mirrored one,
+    // rows i-2..i+4, so the window reaches one row further.
+    constexpr int CTR = SCHEME == 0 ? 1 : 3;
+    constexpr int R = SCHEME == 0 ? 4 : (MIX ? 8 : 7);
+    constexpr int AH = R - 1 - CTR;  // look-ahead distance
     constexpr int NC = 4;                   // components of one species
     constexpr bool AUX0 = STAGE != 0;       // y, or acc in stage 4
-    constexpr bool AUX1 = false;
+    // WENO7 rows take long enough that the non-window loads of a row can be
+    // issued at its own start; FD rows are short and prefetch everything
+    constexpr bool LATE = SCHEME == 1;
     // The window keeps the stage input as stored; the FP32 form rounds it to
     // FP32 where the right-hand side consumes it, and its stage combine uses
     // the exact FP64 centre value.
-    using Buf = ChunkBuf<TI, B, NC, AUX0, AUX1>;
+    using Buf = RowBuf<TI, NC>;
 
     const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
-    const int sp = q.sp, z0 = q.z0, z1 = q.z1, jl = q.jl;
+    const int sp = q.sp, jl = q.jl;
     const double v = d.vel[jl];
     const double gl = q.lane_on ? d.g[jl] : 0.0;
     const double agl = q.lane_on ? d.agb[jl] : 0.0;
@@ -276,33 +369,43 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     const T tv = (T)v;
     const T cv = (T)(v * (1.0 / 12.0));
     const T ce = (T)d.ko16;
-    const T weps = (T)d.weno_eps;
+    const T epsv = (T)(v != 0.0 ? d.weno_eps / (v * v) : d.weno_eps);
     const bool vpos = v > 0.0;
 
     const size_t plane = d.ps;  // plane stride in elements (padded)
     const int cofs = sp * NC;
     const void *in = STAGE == 0 ? (const void *)d.y : (STAGE == 2 ? d.yb : d.ya);
-    const char *inb = static_cast<const char *>(in) + (size_t)cofs * plane * sizeof(TI);
-    const char *aux0b = reinterpret_cast<const char *>(STAGE == 3 ? d.acc : d.y) + (size_t)cofs * plane * 8;
+    const gchar *inb = (const gchar *)in + (size_t)cofs * plane * sizeof(TI);
+    const gchar *aux0b = (const gchar *)(STAGE == 3 ? d.acc : d.y) + (size_t)cofs * plane * 8;
     constexpr uint32_t out_es = (STAGE == 1 && FORM == 1) ? 4 : 8;  // element size of the stage output
-    char *outb = STAGE == 0 ? static_cast<char *>(d.ya)
-               : STAGE == 1 ? static_cast<char *>(d.yb)
-               : STAGE == 2 ? static_cast<char *>(d.ya) : reinterpret_cast<char *>(d.y);
+    gchar *outb = STAGE == 0 ? (gchar *)d.ya
+                : STAGE == 1 ? (gchar *)d.yb
+                : STAGE == 2 ? (gchar *)d.ya : (gchar *)d.y;
     outb += (size_t)cofs * plane * out_es;
-    char *accw = reinterpret_cast<char *>(d.acc) + (size_t)cofs * plane * 8;
+    gchar *accw = (gchar *)d.acc + (size_t)cofs * plane * 8;
     const size_t pin = plane * sizeof(TI);   // plane strides in bytes
     const size_t p64 = plane * 8;
     const size_t pout = plane * out_es;
-    const double *m_in = STAGE == 0 ? d.mom[0] : STAGE == 1 ? d.mom[1] : STAGE == 2 ? d.mom[2] : d.mom[3];
-    double *m_out = STAGE == 0 ? d.mom[1] : STAGE == 1 ? d.mom[2] : STAGE == 2 ? d.mom[3] : d.mom[0];
+    const gdouble *m_in = (const gdouble *)(STAGE == 0 ? d.mom[0] : STAGE == 1 ? d.mom[1] : STAGE == 2 ? d.mom[2] : d.mom[3]);
+    gdouble *m_out = (gdouble *)(STAGE == 0 ? d.mom[1] : STAGE == 1 ? d.mom[2] : STAGE == 2 ? d.mom[3] : d.mom[0]);
     const int nparts = 2 * vchunks;
-    // WR: one row group per wave (nv > 32), so rows and their moment partials
-    // are wave-uniform and live in scalar registers
+    // lane-distributed partial reads (one row group per wave): lane 16 g + p
+    // reads parts p, p + 16, ... of quantities g and g + 3
+    constexpr bool lanep = WR;
+    const int plog = min(4, 32 - __builtin_clz(nparts - 1));  // DPP steps: log2 of the parts per lane group
+    const int pg = min(l / kPartLanes, 2), pp = min(l % kPartLanes, nparts - 1);
+    const bool p_on = l < 3 * kPartLanes && l % kPartLanes < nparts;
+    const int poff = pp * kMomQ + pg;
 
-    const double dz_inv = d.dz_inv, dt = d.dt, hdt = 0.5 * d.dt, dt6 = d.dt * (1.0 / 6.0);
+    const double dzs = dir > 0 ? d.dz_inv : -d.dz_inv;
+    const double dt = d.dt, hdt = 0.5 * d.dt, dt6 = d.dt * (1.0 / 6.0);
     const double third = 1.0 / 3.0;
     const double mudv = d.mudv, h3vac = d.h3vac, hexvac = d.hexvac, lam = d.lam;
-    const int zend = z0 + d.seg;
+    // WR: rows are wave-uniform and exactly the segment's; otherwise every
+    // group of the wave takes seg steps and rows past a ragged end are not stored
+    const int nrows = q.z1 - q.z0;
+    const int nsteps = WR ? nrows : d.seg;
+    const int start = dir > 0 ? q.z0 : q.z1 - 1;
 
     auto load_row = [&](int row, TI (&dst)[NC]) {
         const uint32_t off = (uint32_t)(row * nv + jl) * (uint32_t)sizeof(TI);
@@ -310,152 +413,204 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         for (int c = 0; c < NC; ++c) dst[c] = ld<TI>(inb + (size_t)c * pin, off);
     };
 
-    // issue every load of the chunk starting at row i0
-    auto issue = [&](int i0, Buf &cb_) {
+    // the moment partials of step k's input row and the FP64 operand of its
+    // stage combine
+    auto issue_side = [&](int k, double (&a0)[NC], double (&S)[kMomQ], double (&pv)[2]) {
+        const int r = start + dir * k;
+        int irow = min(r, nz - 1);
+        if constexpr (WR) irow = __builtin_amdgcn_readfirstlane(irow);
+        const gdouble *mp = m_in + (size_t)irow * nparts * kMomQ;
+        if constexpr (lanep) {
+            // nothing uses the loaded values before the sum (lanes past the
+            // parts are zeroed there), so nothing waits for these loads here
+            pv[0] = mp[poff];
+            pv[1] = mp[poff + 3];
+            for (int pb = kPartLanes; pb < nparts; pb += kPartLanes) {  // nv > 512 only
+                const int pq = pb + l % kPartLanes;
+                const bool on2 = l < 3 * kPartLanes && pq < nparts;
+                const int o2 = min(pq, nparts - 1) * kMomQ + pg;
+                const double x0 = mp[o2], x1 = mp[o2 + 3];
+                pv[0] += on2 ? x0 : 0.0;
+                pv[1] += on2 ? x1 : 0.0;
+            }
+        } else {
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            int irow = min(i0 + b, nz - 1);
-            if constexpr (WR) irow = __builtin_amdgcn_readfirstlane(irow);
-            const double *mp = m_in + (size_t)irow * nparts * kMomQ;
-#pragma unroll
-            for (int k = 0; k < kMomQ; ++k) cb_.S[b][k] = mp[k] + mp[kMomQ + k];
+            for (int m = 0; m < kMomQ; ++m) S[m] = mp[m] + mp[kMomQ + m];
             for (int p = 2; p < nparts; ++p) {
 #pragma unroll
-                for (int k = 0; k < kMomQ; ++k) cb_.S[b][k] += mp[p * kMomQ + k];
+                for (int m = 0; m < kMomQ; ++m) S[m] += mp[p * kMomQ + m];
             }
         }
+        const uint32_t off = (uint32_t)(irow * nv + jl) * 8u;
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            // rows past a ragged segment end are not produced; their look-ahead
-            // stays on the last produced row (always inside [0, 2 nz))
-            const int ahead = min(i0 + b + H, z1 - 1 + H);
-            TI tmp[NC];
-            load_row(wrap_row(ahead, nz), tmp);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) cb_.nw[c][b] = tmp[c];
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const uint32_t off = (uint32_t)(min(i0 + b, nz - 1) * nv + jl) * 8u;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                if constexpr (AUX0) cb_.a0[b][c] = ld<double>(aux0b + (size_t)c * p64, off);
-            }
+        for (int c = 0; c < NC; ++c) {
+            if constexpr (AUX0) a0[c] = ld<double>(aux0b + (size_t)c * p64, off);
         }
     };
+    // the window row entering at step k
+    auto issue_ahead = [&](int k, TI (&nw)[NC]) {
+        const int r = start + dir * k;
+        // WR: the look-ahead row lies in [z0 - AH, z1 - 1 + AH].  Otherwise rows
+        // past a ragged segment end are not produced and their look-ahead stays
+        // on the last produced row.  Both stay inside (-nz, 2 nz).
+        const int ahead = WR ? r + dir * AH : min(r + AH, q.z1 - 1 + AH);
+        load_row(wrap_row(ahead, nz), nw);
+    };
+    // loads issued one step ahead (LATE: only the window row; the rest is
+    // loaded at the start of its own step, behind the flux arithmetic)
+    auto issue = [&](int k, Buf &b) {
+        issue_ahead(k, b.nw);
+        if constexpr (!LATE) issue_side(k, b.a0, b.S, b.pv);
+    };
 
-    TI w[NC][R - 1];  // carried window rows i0-H+1 .. i0+H-1
-    T fprev[NC];      // flux at i0-1/2
+    TI w[NC][R - 1];  // carried window rows: w[.][m] is row r + dir (m - CTR)
+    T fprev[NC];      // flux on the face behind the current row
 
-    // the B rows of a chunk: window row m of row i0+b is w (m < R-1-b) or the buffer
-    auto compute = [&](int i0, const Buf &cb_) {
+    auto compute = [&](int k, const Buf &b) {
+        const int r = start + dir * k;
+        const bool row_in = WR || k < nrows;
+        const int irow = min(r, nz - 1);
+        auto win = [&](int c, int m) -> TI {  // window row m of this step, as stored
+            return m < R - 1 ? w[c][m] : b.nw[c];
+        };
+        double la0[NC], lS[kMomQ], lpv[2];
+        if constexpr (LATE) issue_side(k, la0, lS, lpv);
+        const double(&a0)[NC] = LATE ? la0 : b.a0;
+        const double(&S0)[kMomQ] = LATE ? lS : b.S;
+        const double(&pv)[2] = LATE ? lpv : b.pv;
+        double adv[NC];  // flux differences times dir / dz
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const int i = i0 + b;
-            const bool row_in = i < z1;
-            const int irow = min(i, nz - 1);
-            auto win = [&](int c, int m) -> TI {  // window row i-H+1+m, as stored
-                const int k = b + m;              // index in carried ++ buffer
-                return k < R - 1 ? w[c][k] : cb_.nw[c][k - (R - 1)];
-            };
-            const double A0 = cb_.S[b][0] - v * cb_.S[b][3];
-            const double A1 = cb_.S[b][1] - v * cb_.S[b][4];
-            const double A2 = cb_.S[b][2] - v * cb_.S[b][5];
-            const double h3 = h3vac + sgn * (lam + mudv * A0);
-            const double hr = hexvac + sgn * (mudv * A1);
-            const double hi = mudv * A2;
-            double u[NC], kk[NC];  // centre values as the right-hand side sees them
-#pragma unroll
-            for (int c = 0; c < NC; ++c) u[c] = (double)(T)win(c, H - 1);
-            minus_i_commutator(h3, hr, hi, u[0], u[1], u[2], u[3], kk[0], kk[1], kk[2], kk[3]);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                T uu[R];
-#pragma unroll
-                for (int m = 0; m < R; ++m) uu[m] = (T)win(c, m);
-                const T fnew = interface_flux<SCHEME, T>(uu, tv, vpos, cv, ce, weps);
-                kk[c] -= ((double)fnew - (double)fprev[c]) * dz_inv;
-                fprev[c] = fnew;
-            }
-            double o[NC];
-            const uint32_t off64 = (uint32_t)(irow * nv + jl) * 8u;
-            const uint32_t offo = (uint32_t)(irow * nv + jl) * out_es;
-            const bool on = row_in && q.lane_on;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const double centre = (double)win(c, H - 1);  // exact stage input (FP64 except Y3)
-                if constexpr (STAGE == 0) {
-                    o[c] = centre + hdt * kk[c];
-                } else if constexpr (STAGE == 1) {
-                    const double y2 = centre;
-                    o[c] = cb_.a0[b][c] + hdt * kk[c];
-                    if (on) st<double>(accw + (size_t)c * p64, off64, ((cb_.a0[b][c] + y2) + dt * kk[c]) * third);
-                } else if constexpr (STAGE == 2) {
-                    o[c] = cb_.a0[b][c] + dt * kk[c];
-                } else {
-                    const double y4 = centre;
-                    o[c] = (cb_.a0[b][c] + y4 * third) + dt6 * kk[c];
-                }
-                if (on) {
-                    if constexpr (out_es == 8) st<double>(outb + (size_t)c * pout, offo, o[c]);
-                    else st<float>(outb + (size_t)c * pout, offo, (float)o[c]);
-                }
-                if (FORM == 1) o[c] = (double)(float)o[c];  // the next stage sees FP32 values
-                if (!on) o[c] = 0.0;
-            }
-            double mt[kMomQ];
-            species_moment_terms(o, ca, cb, v, mt);
-            write_row_moments(mt, d.lr_log2, row_in && l == (1 << d.lr_log2) - 1,
-                              m_out + (((size_t)irow * vchunks + q.vc) * 2 + sp) * kMomQ);
+        for (int c = 0; c < NC; ++c) {
+            auto x = [&](int m) -> T { return m < R ? (T)win(c, REV ? R - 1 - m : m) : T(0); };
+            const T fnew = interface_flux<SCHEME, MIX, T>(x(0), x(1), x(2), x(3), x(4), x(5), x(6), x(7), tv, vpos, cv,
+                                                          ce, epsv);
+            adv[c] = ((double)fnew - (double)fprev[c]) * dzs;
+            fprev[c] = fnew;
         }
-        // slide: the last R-1 rows of (carried ++ buffer) are carried on
+        double S[kMomQ];
+        if constexpr (lanep) {
+            const double pz[2] = {p_on ? pv[0] : 0.0, p_on ? pv[1] : 0.0};
+            sum_row_parts(pz, plog, S);
+        } else {
+#pragma unroll
+            for (int m = 0; m < kMomQ; ++m) S[m] = S0[m];
+        }
+        const double A0 = S[0] - v * S[3];
+        const double A1 = S[1] - v * S[4];
+        const double A2 = S[2] - v * S[5];
+        const double h3 = h3vac + sgn * (lam + mudv * A0);
+        const double hr = hexvac + sgn * (mudv * A1);
+        const double hi = mudv * A2;
+        double u[NC], kk[NC];  // centre values as the right-hand side sees them
+#pragma unroll
+        for (int c = 0; c < NC; ++c) u[c] = (double)(T)win(c, CTR);
+        minus_i_commutator(h3, hr, hi, u[0], u[1], u[2], u[3], kk[0], kk[1], kk[2], kk[3]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) kk[c] -= adv[c];
+        double o[NC];
+        const uint32_t off64 = (uint32_t)(irow * nv + jl) * 8u;
+        const uint32_t offo = (uint32_t)(irow * nv + jl) * out_es;
+        const bool on = row_in && q.lane_on;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double centre = (double)win(c, CTR);  // exact stage input (FP64 except Y3)
+            if constexpr (STAGE == 0) {
+                o[c] = centre + hdt * kk[c];
+            } else if constexpr (STAGE == 1) {
+                const double y2 = centre;
+                o[c] = a0[c] + hdt * kk[c];
+                if (on) st<double>(accw + (size_t)c * p64, off64, ((a0[c] + y2) + dt * kk[c]) * third);
+            } else if constexpr (STAGE == 2) {
+                o[c] = a0[c] + dt * kk[c];
+            } else {
+                const double y4 = centre;
+                o[c] = (a0[c] + y4 * third) + dt6 * kk[c];
+            }
+            if (on) {
+                if constexpr (out_es == 8) st<double>(outb + (size_t)c * pout, offo, o[c]);
+                else st<float>(outb + (size_t)c * pout, offo, (float)o[c]);
+            }
+            if (FORM == 1) o[c] = (double)(float)o[c];  // the next stage sees FP32 values
+            if (!on) o[c] = 0.0;
+        }
+        double mt[kMomQ];
+        species_moment_terms(o, ca, cb, v, mt);
+        gdouble *dst = m_out + (((size_t)irow * vchunks + q.vc) * 2 + sp) * kMomQ;
+        if constexpr (WR) wave_row_moments(mt, lds, l, dst);
+        else write_row_moments(mt, d.lr_log2, row_in && l == (1 << d.lr_log2) - 1, dst);
+        // slide the window by one row; the entering row is copied into fresh
+        // registers so that the buffer's registers are free for the next load
+        // into it (else the buffer would be moved, after waiting for its
+        // loads, at the loop's back edge)
 #pragma unroll
         for (int m = 0; m < R - 1; ++m) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) w[c][m] = (m + B < R - 1) ? w[c][m + B] : cb_.nw[c][m + B - (R - 1)];
+            for (int c = 0; c < NC; ++c) w[c][m] = m < R - 2 ? w[c][m + 1] : fresh_copy(b.nw[c]);
         }
     };
 
-    // prologue: carried rows z0-H+1 .. z0+H-1 and the row below them, then the
-    // first chunk's loads, then the flux at z0-1/2
+    // prologue: the carried rows and the row behind them, then the first
+    // step's loads, then the flux on the face behind the first row
     TI low[NC];
-    load_row(wrap_row(z0 - H, nz), low);
+    load_row(wrap_row(start - dir * (CTR + 1), nz), low);
 #pragma unroll
     for (int m = 0; m < R - 1; ++m) {
         TI tmp[NC];
-        load_row(wrap_row(z0 - H + 1 + m, nz), tmp);
+        load_row(wrap_row(start + dir * (m - CTR), nz), tmp);
 #pragma unroll
         for (int c = 0; c < NC; ++c) w[c][m] = tmp[c];
     }
     Buf bufA, bufB;
-    issue(z0, bufA);
+    issue(0, bufA);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        T u[R];
-        u[0] = (T)low[c];
-#pragma unroll
-        for (int m = 1; m < R; ++m) u[m] = (T)w[c][m - 1];
-        fprev[c] = interface_flux<SCHEME, T>(u, tv, vpos, cv, ce, weps);
+        auto y = [&](int m) -> T { return m == 0 ? (T)low[c] : (T)w[c][m - 1]; };
+        auto x = [&](int m) -> T { return m < R ? y(REV ? R - 1 - m : m) : T(0); };
+        fprev[c] = interface_flux<SCHEME, MIX, T>(x(0), x(1), x(2), x(3), x(4), x(5), x(6), x(7), tv, vpos, cv, ce,
+                                                  epsv);
     }
-    for (int i0 = z0; i0 < zend; i0 += 2 * B) {
-        if (i0 + B < zend) issue(i0 + B, bufB);
-        compute(i0, bufA);
-        if (i0 + B >= zend) break;
-        if (i0 + 2 * B < zend) issue(i0 + 2 * B, bufA);
-        compute(i0 + B, bufB);
+    for (int k = 0; k < nsteps; k += 2) {
+        if (k + 1 < nsteps) issue(k + 1, bufB);
+        compute(k, bufA);
+        if (k + 1 >= nsteps) break;
+        if (k + 2 < nsteps) issue(k + 2, bufA);
+        compute(k + 1, bufB);
     }
 }
 
+// WENO7 waves whose bins all share one sign of v march in the upwind
+// direction; waves whose bins straddle v = 0 (and every wave of a small-nv
+// grid, whose row groups span all bins) select the stencil per lane.
+// FD waves of odd segments march down z (the window is then mirrored and the
+// flux arguments are taken in reverse), so that two neighbouring segments
+// reach their shared boundary rows at the same time, both at the start or
+// both at the end of their march, and the halo rows are re-read from L2.
+constexpr bool kAltDirFD = true;
 template <int SCHEME, int FORM, int STAGE, bool WR>
-__device__ __forceinline__ void stage_group(const InstDesc &d, int task, int l) {
+__device__ __forceinline__ void stage_group(const InstDesc &d, int task, int l, double *lds) {
     const GroupGeom q = group_geom(d, task, l);
-    stage_body<SCHEME, FORM, STAGE, kChunkRows[SCHEME], WR>(d, q, l);
+    if constexpr (WR) {
+        if (q.z1 <= q.z0) return;  // wave-uniform
+        if constexpr (SCHEME == 1) {
+            const double v = d.vel[q.jl];
+            const bool any_pos = __ballot(q.lane_on && v > 0.0) != 0;
+            const bool any_neg = __ballot(q.lane_on && v < 0.0) != 0;
+            if (any_pos && any_neg) stage_body<SCHEME, FORM, STAGE, true, true, false>(d, q, l, 1, lds);
+            else stage_body<SCHEME, FORM, STAGE, true, false, false>(d, q, l, any_neg ? -1 : 1, lds);
+        } else if (kAltDirFD && (q.segi & 1)) {
+            stage_body<SCHEME, FORM, STAGE, true, false, true>(d, q, l, -1, lds);
+        } else {
+            stage_body<SCHEME, FORM, STAGE, true, false, false>(d, q, l, 1, lds);
+        }
+    } else {
+        stage_body<SCHEME, FORM, STAGE, false, SCHEME == 1, false>(d, q, l, 1, lds);
+    }
 }
 
 // Moment partials of the stage-1 input (the state y) for a freshly set state,
 // with exactly the arithmetic the stage-4 producer uses.
-template <int FORM>
-__device__ __forceinline__ void moments_group(const InstDesc &d, int task, int l) {
+template <int FORM, bool WR>
+__device__ __forceinline__ void moments_group(const InstDesc &d, int task, int l, double *lds) {
     const GroupGeom q = group_geom(d, task, l);
     const int nz = d.nz, nv = d.nv;
     const double v = d.vel[q.jl];
@@ -463,8 +618,9 @@ __device__ __forceinline__ void moments_group(const InstDesc &d, int task, int l
     const double agl = q.lane_on ? d.agb[q.jl] : 0.0;
     const double ca = q.sp ? -agl : gl, cb = q.sp ? agl : gl;
     const size_t plane = d.ps;
-    const double *yb = d.y + (size_t)q.sp * 4 * plane;
-    for (int i = q.z0; i < q.z0 + d.seg; ++i) {
+    const gdouble *yb = (const gdouble *)d.y + (size_t)q.sp * 4 * plane;
+    const int zend = WR ? q.z1 : q.z0 + d.seg;
+    for (int i = q.z0; i < zend; ++i) {
         const bool row_in = i < q.z1;
         const int irow = min(i, nz - 1);
         const size_t at = (size_t)irow * nv + q.jl;
@@ -476,8 +632,9 @@ __device__ __forceinline__ void moments_group(const InstDesc &d, int task, int l
         }
         double mt[kMomQ];
         species_moment_terms(o, ca, cb, v, mt);
-        write_row_moments(mt, d.lr_log2, row_in && l == (1 << d.lr_log2) - 1,
-                          d.mom[0] + (((size_t)irow * d.vchunks + q.vc) * 2 + q.sp) * kMomQ);
+        gdouble *dst = (gdouble *)d.mom[0] + (((size_t)irow * d.vchunks + q.vc) * 2 + q.sp) * kMomQ;
+        if constexpr (WR) wave_row_moments(mt, lds, l, dst);
+        else write_row_moments(mt, d.lr_log2, row_in && l == (1 << d.lr_log2) - 1, dst);
     }
 }
 
@@ -495,27 +652,41 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk, bool reverse) {
     return start + (reverse ? cnt - 1 - kk : kk);
 }
 
+// LDS scratch of the wave-row moment reduction (WR kernels only).
+template <bool WR>
+__device__ __forceinline__ double *wave_lds(double *pool) {
+    return WR ? pool + (threadIdx.x >> 6) * kLdsPerWave : nullptr;
+}
+
+// Register budgets (waves per SIMD): FD 4 (128 VGPRs) with one row group per
+// wave, else 3 (168 VGPRs); WENO7 3, else 2.
+template <int SCHEME, bool WR>
+constexpr int kMinWavesPerSimd = SCHEME == 0 ? (WR ? 4 : 3) : (WR ? 3 : 2);
+
 template <int SCHEME, int FORM, int STAGE, bool WR>
-__global__ __launch_bounds__(kWave *kWavesPerBlock) void stage_kernel(InstDesc d) {
+__global__ __launch_bounds__(kWave *kWavesPerBlock, (kMinWavesPerSimd<SCHEME, WR>)) void stage_kernel(InstDesc d) {
+    __shared__ __align__(16) double pool[WR ? kWavesPerBlock * kLdsPerWave : 2];
     const int lb = xcd_block(blockIdx.x, gridDim.x, (STAGE & 1) != 0);
     const int wave = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & (kWave - 1);
     const int G = kWave >> d.lr_log2;
     const int task = wave * G + (lane >> d.lr_log2);
     if (wave * G >= d.ntasks) return;  // whole wave idle (uniform)
-    if constexpr (WR) stage_group<SCHEME, FORM, STAGE, true>(d, wave, lane);
-    else stage_group<SCHEME, FORM, STAGE, false>(d, task, lane & ((1 << d.lr_log2) - 1));
+    if constexpr (WR) stage_group<SCHEME, FORM, STAGE, true>(d, wave, lane, wave_lds<true>(pool));
+    else stage_group<SCHEME, FORM, STAGE, false>(d, task, lane & ((1 << d.lr_log2) - 1), nullptr);
 }
 
-template <int FORM>
+template <int FORM, bool WR>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void moments_init_kernel(InstDesc d) {
+    __shared__ __align__(16) double pool[WR ? kWavesPerBlock * kLdsPerWave : 2];
     const int lb = xcd_block(blockIdx.x, gridDim.x, false);
     const int wave = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & (kWave - 1);
     const int G = kWave >> d.lr_log2;
     const int task = wave * G + (lane >> d.lr_log2);
     if (wave * G >= d.ntasks) return;
-    moments_group<FORM>(d, task, lane & ((1 << d.lr_log2) - 1));
+    if constexpr (WR) moments_group<FORM, true>(d, wave, lane, wave_lds<true>(pool));
+    else moments_group<FORM, false>(d, task, lane & ((1 << d.lr_log2) - 1), nullptr);
 }
 
 // Batched launch: a fixed grid of waves walks the wave-task list round-robin
@@ -523,17 +694,19 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void moments_init_kernel(Ins
 // instance descriptor, then runs the same group code as a single instance.
 // One kernel per scheme, so each gets its own register budget.
 template <int SCHEME, int FORM, int STAGE, bool WR>
-__global__ __launch_bounds__(kWave *kWavesPerBlock) void batch_stage_kernel(const InstDesc *__restrict__ descs,
+__global__ __launch_bounds__(kWave *kWavesPerBlock, (kMinWavesPerSimd<SCHEME, WR>)) void batch_stage_kernel(const InstDesc *__restrict__ descs,
                                                                            const WaveTask *__restrict__ tasks,
                                                                            int nwt) {
+    __shared__ __align__(16) double pool[WR ? kWavesPerBlock * kLdsPerWave : 2];
     const int nwaves = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & (kWave - 1);
     const int first = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
     for (int wt = first; wt < nwt; wt += nwaves) {
         const WaveTask t = tasks[wt];
         const InstDesc &d = descs[t.inst];
-        if constexpr (WR) stage_group<SCHEME, FORM, STAGE, true>(d, t.task0, lane);
-        else stage_group<SCHEME, FORM, STAGE, false>(d, t.task0 + (lane >> d.lr_log2), lane & ((1 << d.lr_log2) - 1));
+        if constexpr (WR) stage_group<SCHEME, FORM, STAGE, true>(d, t.task0, lane, wave_lds<true>(pool));
+        else stage_group<SCHEME, FORM, STAGE, false>(d, t.task0 + (lane >> d.lr_log2), lane & ((1 << d.lr_log2) - 1),
+                                                     nullptr);
     }
 }
 
@@ -600,8 +773,14 @@ hipError_t launch_stage(const InstDesc &d, int stage, int blocks, hipStream_t st
 
 hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st) {
     const dim3 grid(blocks), block(kWave * kWavesPerBlock);
-    if (d.form == 0) hipLaunchKernelGGL((moments_init_kernel<0>), grid, block, 0, st, d);
-    else hipLaunchKernelGGL((moments_init_kernel<1>), grid, block, 0, st, d);
+    const bool wr = d.lr_log2 == 6;
+    if (d.form == 0) {
+        if (wr) hipLaunchKernelGGL((moments_init_kernel<0, true>), grid, block, 0, st, d);
+        else hipLaunchKernelGGL((moments_init_kernel<0, false>), grid, block, 0, st, d);
+    } else {
+        if (wr) hipLaunchKernelGGL((moments_init_kernel<1, true>), grid, block, 0, st, d);
+        else hipLaunchKernelGGL((moments_init_kernel<1, false>), grid, block, 0, st, d);
+    }
     return hipGetLastError();
 }
 

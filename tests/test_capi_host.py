@@ -61,6 +61,7 @@ def test_null_handles_and_errors():
     assert L.cosenu_step(None, 1) == cosenu.ESTATE
     assert L.cosenu_sync(None) == cosenu.ESTATE
     assert L.cosenu_batch_step(None, 1) == cosenu.ESTATE
+    assert L.cosenu_get_rows(None, 0, 1, None, 0) == cosenu.ESTATE
     assert L.cosenu_params_default(None) == cosenu.EINVAL
     assert L.cosenu_batch_create(None, 0, None) == cosenu.EINVAL
     for code in (0, -1, -2, -3, -4, -5):

@@ -66,3 +66,30 @@ def test_fv_65536x256_windows(prec):
         err = np.abs(got - ref).max()
         print(f"precision {prec}, window at {a}: max abs {err:.3e}")
         assert err <= (1e-12 if prec == wl.FP64 else 1e-7), (a, err)
+
+
+def test_fv_1048576x512_windows_fp32acc():
+    """The 2^20 x 512 WENO7 case (omega = 1e-3, lambda = 10) in its FP32 form,
+    checked on periodic slabs fetched with get_rows: one oracle step on the
+    slab against the GPU step on the slab interior, at the perturbation, at the
+    periodic seam and at a random place."""
+    w = wl.fv_1m_x512(5, wl.FP32_ACC64)
+    nz = w["nz"]
+    margin, width = 16, 32
+    rng = np.random.default_rng(1)
+    starts = [nz // 2 - width // 2, nz - width // 2, int(rng.integers(0, nz))]
+    with cosenu.Sim(w) as s:
+        s.autotune()
+        s.step(10)
+        slabs = [s.get_rows(a - margin, width + 2 * margin) for a in starts]
+        s.step(1)
+        outs = [s.get_rows(a, width) for a in starts]
+        dt = s.info()["dt"]
+    for a, slab, got in zip(starts, slabs, outs):
+        p = o.problem_from_workload(dict(w, nz=width + 2 * margin, L=(width + 2 * margin) * (w["L"] / nz)))
+        assert abs(p.dt - dt) < 1e-15
+        ref = o.rk4(p, slab, 1)[:, margin:margin + width, :]
+        err = np.abs(got - ref).max()
+        print(f"window at {a}: max abs {err:.3e}")
+        assert err <= 1e-7, (a, err)
+        assert np.isfinite(got).all()

@@ -54,6 +54,21 @@ def test_get_set_roundtrip_and_clock():
         assert s.conserved()["Pee_nu"] != 0.0
 
 
+def test_get_rows_is_a_periodic_slab_of_get_state():
+    w = wl.small_fd(1)
+    y = wl.random_state(512, 32, seed=4)
+    with cosenu.Sim(w) as s:
+        s.set_state(y)
+        s.step(3)
+        full = s.get_state()
+        for z0, n in ((0, 512), (5, 17), (500, 40), (-3, 9), (1024 + 7, 1), (511, 512)):
+            rows = np.arange(z0, z0 + n) % 512
+            assert np.array_equal(s.get_rows(z0, n), full[:, rows, :]), (z0, n)
+        for z0, n in ((0, 0), (0, 513)):
+            with pytest.raises(cosenu.CosenuError):
+                s.get_rows(z0, n)
+
+
 def test_batch_instances_equal_solo_runs():
     ws = []
     for i, (scheme, nz, nv) in enumerate([(0, 300, 32), (1, 257, 64), (0, 190, 100), (1, 64, 16), (0, 1000, 8)]):
