@@ -64,6 +64,8 @@ hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st);
 // wave_rows: every instance of the task list has nv > 32 (one row group per wave)
 hipError_t launch_batch_stage(const InstDesc *d_descs, const WaveTask *d_tasks, int nwaves, int scheme, int form,
                               bool wave_rows, int stage, int blocks, hipStream_t st);
+// resident waves per CU of the batch stage kernels of one variant (the least over the four stages)
+int batch_waves_per_cu(int scheme, int form, bool wave_rows);
 // ---- diagnostics (diag_kernels.hip) ----------------------------------------
 // per (segment, chunk) partials [nrowtasks][kDiagQ]:
 //   0..3 M0 (trace, x, y, z) summed g P - alpha gbar Pbar~ (without dz dv)

@@ -34,6 +34,7 @@
 // 8 components per cell and step.  In the FP32 form Y3 is stored in FP32 (Y2
 // and Y4 carry k1 and k3 and stay FP64) and every stage input is rounded to
 // FP32 before the stencil, so its right-hand side is evaluated on FP32 values.
+#include <algorithm>
 #include <type_traits>
 
 #include "cosenu_internal.h"
@@ -303,13 +304,14 @@ struct RowBuf {
 };
 
 // The moment partials of an input row come from nparts = 2 vchunks producer
-// groups.  With one row group per wave and nparts <= 16 they are read
-// lane-distributed: lane 16 g + p holds part p of quantities g and g + 3 (zero
-// past the parts), one load per lane and quantity pair, and are summed only
-// where they are used, so that their load never forces an early wait on the
-// loads issued after it.  A DPP sum over the 16 lanes of each g (p in pairs,
-// then pairs of pairs; a fixed order) leaves every lane of the group with the
-// totals, which are then read as wave-uniform values.
+// groups.  With one row group per wave they are read lane-distributed: lane
+// 16 g + p holds part p of quantities g and g + 3 (zero past the parts; parts
+// p + 16, p + 32, ... are added to it at load time, which only nv > 512 needs),
+// one load per lane and quantity pair, and they are summed only where they are
+// used, so that their load never forces an early wait on the loads issued
+// after it.  A DPP sum over the 16 lanes of each g (p in pairs, then pairs of
+// pairs; a fixed order) leaves every lane of the group with the totals, which
+// are then read as wave-uniform values.
 constexpr int kPartLanes = 16;
 
 __device__ __forceinline__ double readlane_f64(double x, int lane) {
@@ -334,9 +336,10 @@ __device__ __forceinline__ void sum_row_parts(const double pv[2], int plog, doub
 // moment partials) are in flight; two buffers alternate so that the arithmetic
 // reads straight from the buffer registers and no copy forces an early wait.
 // Step k handles row start + dir k.  dir = +1 marches up z from z0; dir = -1
-// (WENO7 waves whose bins all have v < 0) marches down from z1 - 1, with the
-// window mirrored so that it is in upwind order; the flux then produced at each
-// step is the one on the lower face, hence the sign of dzs.
+// marches down from z1 - 1 with the window mirrored (WENO7 waves whose bins all
+// have v < 0, so that the window is in upwind order; FD waves of odd segments,
+// whose flux then takes its arguments in reverse, REV).  The flux produced at
+// each step is the one on the face ahead in the march, hence the sign of dzs.
 template <int SCHEME, int FORM, int STAGE, bool WR, bool MIX, bool REV>
 __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q, int l, int dir, double *lds) {
     constexpr bool IN32 = FORM == 1 && STAGE == 2;  // Y3 of the FP32 form is stored in FP32
@@ -344,16 +347,14 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     using TI = typename std::conditional<IN32, float, double>::type;      // stage input as stored
     // Window: R rows around the current one, slot m holding row r + dir (m - CTR).
     // FD needs rows i-1..i+2 of the face i+1/2.  WENO7 needs rows i-3..i+3 of
-    // the upwind-ordered stencil; with MIX a lane may need the mirrored one,
-    // rows i-2..i+4, so the window reaches one row further.
+    // the upwind-ordered stencil when it marches upwind; with MIX a lane may
+    // need the mirrored one, and against the upwind direction (REV) every lane
+    // does, rows i-2..i+4, so the window reaches one row further.
     constexpr int CTR = SCHEME == 0 ? 1 : 3;
-    constexpr int R = SCHEME == 0 ? 4 : (MIX ? 8 : 7);
+    constexpr int R = SCHEME == 0 ? 4 : (MIX || REV ? 8 : 7);
     constexpr int AH = R - 1 - CTR;  // look-ahead distance
     constexpr int NC = 4;                   // components of one species
     constexpr bool AUX0 = STAGE != 0;       // y, or acc in stage 4
-    // WENO7 rows take long enough that the non-window loads of a row can be
-    // issued at its own start; FD rows are short and prefetch everything
-    constexpr bool LATE = SCHEME == 1;
     // The window keeps the stage input as stored; the FP32 form rounds it to
     // FP32 where the right-hand side consumes it, and its stage combine uses
     // the exact FP64 centre value.
@@ -456,11 +457,10 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         const int ahead = WR ? r + dir * AH : min(r + AH, q.z1 - 1 + AH);
         load_row(wrap_row(ahead, nz), nw);
     };
-    // loads issued one step ahead (LATE: only the window row; the rest is
-    // loaded at the start of its own step, behind the flux arithmetic)
+    // every load of step k, issued one step ahead
     auto issue = [&](int k, Buf &b) {
         issue_ahead(k, b.nw);
-        if constexpr (!LATE) issue_side(k, b.a0, b.S, b.pv);
+        issue_side(k, b.a0, b.S, b.pv);
     };
 
     TI w[NC][R - 1];  // carried window rows: w[.][m] is row r + dir (m - CTR)
@@ -473,11 +473,9 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         auto win = [&](int c, int m) -> TI {  // window row m of this step, as stored
             return m < R - 1 ? w[c][m] : b.nw[c];
         };
-        double la0[NC], lS[kMomQ], lpv[2];
-        if constexpr (LATE) issue_side(k, la0, lS, lpv);
-        const double(&a0)[NC] = LATE ? la0 : b.a0;
-        const double(&S0)[kMomQ] = LATE ? lS : b.S;
-        const double(&pv)[2] = LATE ? lpv : b.pv;
+        const double(&a0)[NC] = b.a0;
+        const double(&S0)[kMomQ] = b.S;
+        const double(&pv)[2] = b.pv;
         double adv[NC];  // flux differences times dir / dz
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -578,14 +576,16 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     }
 }
 
-// WENO7 waves whose bins all share one sign of v march in the upwind
-// direction; waves whose bins straddle v = 0 (and every wave of a small-nv
-// grid, whose row groups span all bins) select the stencil per lane.
-// FD waves of odd segments march down z (the window is then mirrored and the
-// flux arguments are taken in reverse), so that two neighbouring segments
-// reach their shared boundary rows at the same time, both at the start or
-// both at the end of their march, and the halo rows are re-read from L2.
-constexpr bool kAltDirFD = true;
+// Direction of march.  Waves of neighbouring segments march in opposite
+// directions, so that they reach their shared boundary rows at the same time
+// (both at the start or both at the end of their march) and the halo rows are
+// re-read from L2.  FD: even segments march up z, odd ones down (the flux then
+// takes its window arguments in reverse).  WENO7 waves whose bins all share
+// one sign of v: even segments march upwind (window in upwind order, 7 rows),
+// odd ones against it (8 rows, arguments in reverse).  WENO7 waves whose bins
+// straddle v = 0 (and every wave of a small-nv grid, whose row groups span all
+// bins) march up z and select the stencil per lane.
+constexpr bool kAltDir = true;
 template <int SCHEME, int FORM, int STAGE, bool WR>
 __device__ __forceinline__ void stage_group(const InstDesc &d, int task, int l, double *lds) {
     const GroupGeom q = group_geom(d, task, l);
@@ -595,9 +595,11 @@ __device__ __forceinline__ void stage_group(const InstDesc &d, int task, int l, 
             const double v = d.vel[q.jl];
             const bool any_pos = __ballot(q.lane_on && v > 0.0) != 0;
             const bool any_neg = __ballot(q.lane_on && v < 0.0) != 0;
+            const int up = any_neg ? -1 : 1;
             if (any_pos && any_neg) stage_body<SCHEME, FORM, STAGE, true, true, false>(d, q, l, 1, lds);
-            else stage_body<SCHEME, FORM, STAGE, true, false, false>(d, q, l, any_neg ? -1 : 1, lds);
-        } else if (kAltDirFD && (q.segi & 1)) {
+            else if (kAltDir && (q.segi & 1)) stage_body<SCHEME, FORM, STAGE, true, false, true>(d, q, l, -up, lds);
+            else stage_body<SCHEME, FORM, STAGE, true, false, false>(d, q, l, up, lds);
+        } else if (kAltDir && (q.segi & 1)) {
             stage_body<SCHEME, FORM, STAGE, true, false, true>(d, q, l, -1, lds);
         } else {
             stage_body<SCHEME, FORM, STAGE, true, false, false>(d, q, l, 1, lds);
@@ -782,6 +784,32 @@ hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st) {
         else hipLaunchKernelGGL((moments_init_kernel<1, false>), grid, block, 0, st, d);
     }
     return hipGetLastError();
+}
+
+namespace {
+template <int SCHEME, int FORM, bool WR>
+int batch_waves_per_cu_t() {
+    int lo = 1 << 30;
+    auto one = [&](const void *fn) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWave * kWavesPerBlock, 0) == hipSuccess && nb > 0)
+            lo = std::min(lo, nb * kWavesPerBlock);
+    };
+    one(reinterpret_cast<const void *>(batch_stage_kernel<SCHEME, FORM, 0, WR>));
+    one(reinterpret_cast<const void *>(batch_stage_kernel<SCHEME, FORM, 1, WR>));
+    one(reinterpret_cast<const void *>(batch_stage_kernel<SCHEME, FORM, 2, WR>));
+    one(reinterpret_cast<const void *>(batch_stage_kernel<SCHEME, FORM, 3, WR>));
+    return lo == (1 << 30) ? 2 * kWavesPerBlock : lo;
+}
+template <bool WR>
+int batch_waves_per_cu_w(int scheme, int form) {
+    if (scheme == 0) return form == 0 ? batch_waves_per_cu_t<0, 0, WR>() : batch_waves_per_cu_t<0, 1, WR>();
+    return form == 0 ? batch_waves_per_cu_t<1, 0, WR>() : batch_waves_per_cu_t<1, 1, WR>();
+}
+}  // namespace
+
+int batch_waves_per_cu(int scheme, int form, bool wave_rows) {
+    return wave_rows ? batch_waves_per_cu_w<true>(scheme, form) : batch_waves_per_cu_w<false>(scheme, form);
 }
 
 hipError_t launch_batch_stage(const InstDesc *d_descs, const WaveTask *d_tasks, int nwt, int scheme, int form,

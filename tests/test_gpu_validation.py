@@ -1,0 +1,141 @@
+"""The paper's validation problems (Sec. 4) run on the HIP kernels through the
+C ABI and checked against closed forms, not against the oracle: with mu = 0
+the equations decouple into advection (Sec. 4.1) and vacuum oscillation
+(Sec. 4.2).
+
+* FD4 + Kreiss-Oliger with RK4 is linear and shift-invariant: the kernels must
+  reproduce the exact Fourier propagator of the scheme on arbitrary data.
+* In the linear-weight limit WENO7 is linear too, with the eq:f7 weights
+  (golden fixture) on the upwind side.
+* Measured orders on a smooth profile: 7 (FV WENO7), 4 (central FD), 3 (FD
+  with Kreiss-Oliger), as Sec. 4.1 states.
+* Vacuum oscillation of a Gaussian packet (eq:vac_sols) and the minimum of the
+  survival probability printed in Sec. 4.2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+from paper_2203_12866_amd import cosenu
+from paper_2203_12866_amd import workloads as wl
+from tests.golden.fixtures import key_values, weno7_linear_coefficients
+from tests.test_oracle_advection import spectral_evolve
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(nz, nv, L, cfl, scheme, precision=wl.FP64, **kw):
+    w = dict(wl.small_fd(1), nz=nz, nv=nv, L=L, cfl=cfl, mu=0.0, omega=0.0, lam=0.0, scheme=scheme,
+             precision=precision)
+    w.update(kw)
+    return cosenu.Sim(w)
+
+
+def _run(nz, nv, L, cfl, scheme, y0, steps, precision=wl.FP64, **kw):
+    with _sim(nz, nv, L, cfl, scheme, precision, **kw) as s:
+        s.set_state(y0)
+        s.step(steps)
+        return s.get_state(), s.info()["dt"]
+
+
+@pytest.mark.parametrize("ko_eps", [0.0, 0.1])
+def test_fd_ko_kernels_match_fourier_propagator(ko_eps):
+    nz, nv, L = 48, 4, 30.0
+    dz = L / nz
+    steps = 25
+    y0 = np.random.default_rng(3).uniform(-1, 1, size=(8, nz, nv))
+    y, dt = _run(nz, nv, L, 0.2775, wl.FD_KO, y0, steps, ko_eps=ko_eps)
+    v = o.velocities(nv)
+    for c in range(8):
+        for j in range(nv):
+            sym = lambda th: (-1j * v[j] * (8 * np.sin(th) - np.sin(2 * th)) / (6 * dz)
+                              - (ko_eps / dz) * np.sin(th / 2) ** 4)
+            expect = spectral_evolve(y0[c, :, j], sym, dt, steps)
+            np.testing.assert_allclose(y[c, :, j], expect, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("nv", [4, 256])
+def test_weno7_kernels_linear_limit_match_fourier_propagator(nv):
+    # nv = 4: row groups span both signs of v (per-lane upwind selection);
+    # nv = 256: whole waves march in their upwind direction
+    cf = weno7_linear_coefficients()
+    nz, L = 40, 20.0
+    dz = L / nz
+    steps = 20
+    amp = 1e-12
+    y0 = amp * np.random.default_rng(4).uniform(-1, 1, size=(8, nz, nv))
+    y, dt = _run(nz, nv, L, 0.3, wl.FV_WENO7, y0, steps)
+    v = o.velocities(nv)
+    for c in range(8):
+        for j in range(0, nv, max(1, nv // 16)):
+            if v[j] > 0:
+                sym = lambda th: -(v[j] / dz) * (1 - np.exp(-1j * th)) * sum(
+                    float(cf[m]) * np.exp(1j * m * th) for m in range(-3, 4))
+            else:
+                sym = lambda th: -(v[j] / dz) * (np.exp(1j * th) - 1) * sum(
+                    float(cf[m]) * np.exp(-1j * m * th) for m in range(-3, 4))
+            expect = spectral_evolve(y0[c, :, j], sym, dt, steps)
+            np.testing.assert_allclose(y[c, :, j], expect, rtol=0, atol=1e-10 * amp)
+
+
+def _advection_error(nz, scheme, ko_eps, dt, T, amp=1.0):
+    L, nv = 1.0, 2  # bins at v = -0.5 and +0.5
+    dz = L / nz
+    z = o.positions(nz, L)
+    prof = lambda x: amp * np.exp(np.sin(2 * math.pi * x / L))
+    y0 = np.zeros((8, nz, nv))
+    y0[0, :, 0] = prof(z)
+    y0[0, :, 1] = prof(z)
+    nsteps = int(round(T / dt))
+    y, dt_gpu = _run(nz, nv, L, dt * 0.5 / dz, scheme, y0, nsteps, ko_eps=ko_eps)
+    assert abs(dt_gpu - dt) < 1e-15
+    t = nsteps * dt
+    return max(math.sqrt(np.mean((y[0, :, j] - prof(z - v * t)) ** 2)) for j, v in ((0, -0.5), (1, 0.5)))
+
+
+def test_kernel_convergence_orders_match_paper():
+    orders = key_values("advection_orders.txt")
+    T = 0.5
+    dt = 0.05 * (1.0 / 64) / 0.5
+    e = [_advection_error(n, wl.FV_WENO7, 0.0, dt, T, amp=1e-4) for n in (16, 32, 64)]
+    assert abs(math.log2(e[1] / e[2]) - orders["fv_weno7"]) < 0.4, e
+    dt = 0.1 * (1.0 / 128) / 0.5
+    e = [_advection_error(n, wl.FD_KO, 0.0, dt, T) for n in (32, 64, 128)]
+    assert abs(math.log2(e[1] / e[2]) - orders["fd_central"]) < 0.3, e
+    e_ko = [_advection_error(n, wl.FD_KO, 0.1, dt, T) for n in (64, 128)]
+    assert e_ko[1] > e[2]
+    assert abs(math.log2(e_ko[0] / e_ko[1]) - 3.0) < 0.3, e_ko
+
+
+@pytest.mark.parametrize("scheme", [wl.FD_KO, wl.FV_WENO7])
+@pytest.mark.parametrize("precision", [wl.FP64, wl.FP32_ACC64])
+def test_kernels_vacuum_oscillation_match_eq_vac_sols(scheme, precision):
+    g = key_values("vacuum_oscillation.txt")
+    omega, theta, v = g["omega"], g["theta_deg"] * math.pi / 180.0, g["v"]
+    nz, nv, L = 2000, 2, 200.0
+    z = o.positions(nz, L)
+    prof = np.exp(-z ** 2 / (2 * 5.0 ** 2))
+    y0 = np.zeros((8, nz, nv))
+    y0[0, :, 1] = prof  # pure nu_e packet in the v = +0.5 bin
+    with _sim(nz, nv, L, 0.2, scheme, precision, omega=omega, theta=theta) as s:
+        dt = s.info()["dt"]
+        steps = int(round(math.pi / omega / dt))  # half a vacuum period
+        s.set_state(y0)
+        s.step(steps)
+        y = s.get_state()
+    t = steps * dt
+    shifted = np.exp(-(z - v * t) ** 2 / (2 * 5.0 ** 2))
+    s2, c2 = math.sin(2 * theta), math.cos(2 * theta)
+    sn2 = math.sin(omega * t / 2) ** 2
+    expect = {0: shifted * (1 - s2 ** 2 * sn2), 1: shifted * (s2 ** 2 * sn2),
+              2: -shifted * (s2 * c2 * sn2), 3: shifted * 0.5 * s2 * math.sin(omega * t)}
+    tol = 1e-6 if precision == wl.FP64 else 1e-5
+    for c, ex in expect.items():
+        e2 = math.sqrt(np.mean((y[c, :, 1] - ex) ** 2))
+        print(f"scheme {scheme} precision {precision} component {c}: E2 {e2:.2e}")
+        assert e2 < tol, (c, e2)
+    surv = y[0, :, 1].sum() / y0[0, :, 1].sum()
+    assert abs(surv - (1 - s2 ** 2 * sn2)) < tol
+    assert abs(surv - g["min_survival"]) < 0.5 * 10 ** (-g["min_survival_digits"])
