@@ -216,6 +216,14 @@ int cosenu_batch_set_state(cosenu_batch *b, int32_t i, const double *in, size_t 
 int cosenu_batch_conserved(cosenu_batch *b, int32_t i, cosenu_conserved_t *out);
 int cosenu_batch_info(cosenu_batch *b, int32_t i, cosenu_info_t *out);
 int cosenu_batch_time_steps(cosenu_batch *b, int64_t nsteps, double *ms);
+/* Batch autotuner: chooses the segment length of every kernel variant of the
+ * batch (variant 2*scheme + (nv > 32)) by timing stages 1-3 of that variant
+ * alone for seg in {4, 8, ..., 128}; every instance of a variant takes the same
+ * length (at most its nz).  Then rebuilds the task lists and re-captures the
+ * step graphs.  States, clocks and results are unchanged (results do not
+ * depend on the segment length).  seg_rows, if not NULL, receives 4 values
+ * (0 for variants absent from the batch).  Synchronises the handle's stream. */
+int cosenu_batch_autotune(cosenu_batch *b, int32_t *seg_rows);
 const char *cosenu_batch_last_error(const cosenu_batch *b);
 
 #ifdef __cplusplus

@@ -123,6 +123,7 @@ def _lib():
             "cosenu_batch_conserved": (ctypes.c_int, [vp, i32, ctypes.POINTER(Conserved)]),
             "cosenu_batch_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(Info)]),
             "cosenu_batch_time_steps": (ctypes.c_int, [vp, i64, dp]),
+            "cosenu_batch_autotune": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
             "cosenu_batch_last_error": (ctypes.c_char_p, [vp]),
         }
         for name, (res, args) in sigs.items():
@@ -301,6 +302,12 @@ class Batch:
         except Exception:
             pass
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
     def __len__(self):
         return len(self.shapes)
 
@@ -339,3 +346,9 @@ class Batch:
         ms = ctypes.c_double()
         self._check(_lib().cosenu_batch_time_steps(self._h, int(n), ctypes.byref(ms)), "cosenu_batch_time_steps")
         return ms.value
+
+    def autotune(self) -> list:
+        """Segment length per kernel variant (2*scheme + (nv > 32)); 0 where absent."""
+        segs = (ctypes.c_int32 * 4)()
+        self._check(_lib().cosenu_batch_autotune(self._h, segs), "cosenu_batch_autotune")
+        return list(segs)

@@ -91,6 +91,24 @@ def test_batch_instances_equal_solo_runs():
         b.close()
 
 
+def test_batch_autotune_keeps_states_and_results():
+    insts = [dict(wl.small_fd(1), nz=300, nv=128), dict(wl.small_fd(2), nz=97, nv=32, scheme=wl.FV_WENO7),
+             dict(wl.small_fd(3), nz=160, nv=256, scheme=wl.FV_WENO7), dict(wl.small_fd(4), nz=64, nv=64)]
+    insts = [dict(w, precision=wl.FP32_ACC64) for w in insts]
+    with cosenu.Batch(insts) as b:
+        b.step(3)
+        before = [b.get_state(i) for i in range(len(insts))]
+        segs = b.autotune()
+        assert all(np.array_equal(b.get_state(i), before[i]) for i in range(len(insts)))
+        assert segs[0] == 0 and all(s > 0 for s in segs[1:]), segs
+        b.step(7)
+        got = [b.get_state(i) for i in range(len(insts))]
+    for w, g in zip(insts, got):
+        with cosenu.Sim(w) as s:
+            s.step(10)
+            assert np.array_equal(s.get_state(), g)
+
+
 def test_torch_stream_binding():
     import torch
     w = wl.small_fd(2)
