@@ -57,9 +57,10 @@ def measured_traffic(workload: str, form: str):
     return None if e is None else e.get("bytes_per_launch")
 
 
-def run_form(cosenu, torch, w, steps, warmup, seg, stage_steps):
+def run_form(cosenu, torch, w, steps, warmup, seg, stage_steps, fused=True):
     sim = cosenu.Sim(w)
     sim.bind_torch_stream()
+    sim.set_fusion(fused)
     chosen = sim.autotune() if seg is None else seg
     if seg is not None:
         sim.set_seg_rows(seg)
@@ -75,15 +76,17 @@ def run_form(cosenu, torch, w, steps, warmup, seg, stage_steps):
     state = sim.get_state()
     sim.close()
     cells = w["nz"] * w["nv"]
-    # average stage-launch duration over the timed region: HIP events on the
-    # sim's stream around the K graph launches (4 stage launches per step)
-    launch_s = ev_ms / (4.0 * steps) / 1e3
+    # average launch duration over the timed region: HIP events on the sim's
+    # stream around the K graph launches (4 single stages or 2 fused stage
+    # pairs per step)
+    nl = info["launches_per_step"]
+    launch_s = ev_ms / (nl * steps) / 1e3
     return dict(seg=chosen, wall=wall, ev_ms=ev_ms, stage_ms=stage_ms, info=info, state=state,
-                updates=cells * 4.0 * steps / wall,
+                updates=cells * 4.0 * steps / wall, launches=nl,
                 gbps_model=info["bytes_per_step"] * steps / wall / 1e9,
                 launch_s=launch_s,
-                stage_us=[m * 1e3 / stage_steps for m in stage_ms],
-                achieved_gbps=info["bytes_per_step"] / 4.0 / launch_s / 1e9)
+                stage_us=[m * 1e3 / stage_steps for m in stage_ms[:nl]],
+                achieved_gbps=info["bytes_per_step"] / nl / launch_s / 1e9)
 
 
 def _oracle_sample(o, w, rows, steps):
@@ -207,6 +210,7 @@ def main():
     ap.add_argument("--seg-rows", type=int, default=None, help="fixed launch shape (default: autotune)")
     ap.add_argument("--stage-steps", type=int, default=50, help="steps timed launch by launch (eager, per-stage breakdown)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fusion", action="store_true", help="four single-stage launches per step")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     args = ap.parse_args()
 
@@ -226,12 +230,22 @@ def main():
     mk = WORKLOADS[args.workload]
     res = {}
     for form, prec in FORMS.items():
-        res[form] = run_form(cosenu, torch, mk(prec), args.steps, args.warmup, args.seg_rows, args.stage_steps)
+        res[form] = run_form(cosenu, torch, mk(prec), args.steps, args.warmup, args.seg_rows, args.stage_steps,
+                             fused=not args.no_fusion)
         print(f"[bench] {args.workload} {form}: {res[form]['updates']:.4e} upd/s, "
-              f"{res[form]['gbps_model']:.0f} GB/s modelled, seg {res[form]['seg']}", file=sys.stderr, flush=True)
+              f"{res[form]['gbps_model']:.0f} GB/s modelled, seg {res[form]['seg']}, "
+              f"{res[form]['launches']} launches/step", file=sys.stderr, flush=True)
+    single = None
+    if res["fp32acc"]["launches"] == 2:  # the same form on four single-stage launches, for comparison
+        single = run_form(cosenu, torch, mk(1), args.steps, args.warmup, args.seg_rows, args.stage_steps, fused=False)
+        print(f"[bench] {args.workload} fp32acc single stages: {single['updates']:.4e} upd/s", file=sys.stderr,
+              flush=True)
 
     head = res["fp32acc"]
     w = mk(1)
+    pairs = head["launches"] == 2
+    kname = ("pair_kernel<FD,FP32acc> (stages 1+2 and 3+4 fused)" if pairs else
+             "stage_kernel<FD,FP32acc>" if w["scheme"] == 0 else "stage_kernel<WENO7,FP32acc>")
     a, b = res["fp32acc"]["state"], res["fp64"]["state"]
     fp32_vs_fp64 = {
         "max_abs": float(np.abs(a - b).max()),
@@ -262,10 +276,11 @@ def main():
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
             "frac": head["achieved_gbps"] / PEAK_HBM_GBPS,
-            "traffic": measured_traffic(args.workload, "fp32acc"),
-            "kernel": "stage_kernel<FD,FP32acc>" if w["scheme"] == 0 else "stage_kernel<WENO7,FP32acc>",
+            "traffic": measured_traffic(args.workload, "fp32acc" + ("/pairs" if pairs else "")),
+            "kernel": kname,
+            "launches_per_step": head["launches"],
             "avg_launch_us": head["launch_s"] * 1e6,
-            "stage_us_eager": head["stage_us"],
+            "launch_us_eager": head["stage_us"],
         },
         "fp64_form": {
             "value": res["fp64"]["updates"],
@@ -275,12 +290,20 @@ def main():
             "roofline_achieved_gbps": res["fp64"]["achieved_gbps"],
             "roofline_frac": res["fp64"]["achieved_gbps"] / PEAK_HBM_GBPS,
             "avg_launch_us": res["fp64"]["launch_s"] * 1e6,
-            "stage_us_eager": res["fp64"]["stage_us"],
+            "launch_us_eager": res["fp64"]["stage_us"],
+            "launches_per_step": res["fp64"]["launches"],
             "seg_rows": res["fp64"]["seg"],
         },
         "fp32_speedup_over_fp64": head["updates"] / res["fp64"]["updates"],
         "fp32_vs_fp64_after_run": fp32_vs_fp64,
     }
+    if single is not None:
+        out["fp32acc_single_stages"] = {
+            "value": single["updates"], "ms_per_step": single["wall"] * 1e3 / args.steps,
+            "bytes_per_update": single["info"]["bytes_per_step"] / (w["nz"] * w["nv"] * 4.0),
+            "roofline_achieved_gbps": single["achieved_gbps"], "seg_rows": single["seg"],
+            "bitwise_equal_to_fused": bool(np.array_equal(single["state"], head["state"])),
+        }
     if not args.no_cpu_baseline:
         cb, errs = cpu_baseline(cosenu, mk(0), args.cpu_budget)
         out["cpu_baseline"] = cb

@@ -128,6 +128,7 @@ typedef struct {
     int32_t v_chunks;        /* 64-bin chunks per row (1 when nv <= 64)        */
     int32_t blocks_per_stage;/* workgroups of one stage launch                 */
     double bytes_per_step;   /* algorithmic HBM bytes of one RK4 step          */
+    int32_t launches_per_step; /* 4 single stages, or 2 fused stage pairs      */
 } cosenu_info_t;
 
 /* Fills *p with the paper's fiducial values (Sec. 5): nz = 512, nv = 32,
@@ -184,17 +185,28 @@ int cosenu_set_stream(cosenu_sim *s, void *hip_stream);
  * Results do not depend on it (bitwise). */
 int cosenu_set_seg_rows(cosenu_sim *s, int32_t seg_rows);
 
+/* Stage fusion (on = 1, the default; 0 = off).  With FD + KO and
+ * 32 < nv <= 256 an RK4 step then runs as two fused launches, stages 1 + 2 and
+ * stages 3 + 4: the intermediate stage values Y2 and Y4 stay on chip and the
+ * moments of the intermediate stage are exchanged between the waves of a
+ * workgroup, which cuts the algorithmic bytes per step from 768 to 448 (FP64)
+ * or from 704 to 384 (FP32 form).  Other shapes and schemes run four single
+ * stages either way.  Results are bitwise those of four single stages.
+ * Synchronises the handle's stream; cosenu_info reports launches_per_step. */
+int cosenu_set_fusion(cosenu_sim *s, int32_t on);
+
 /* Times nsteps steps on the handle's stream with HIP events (after the work
  * already queued) and returns the elapsed milliseconds; synchronises. */
 int cosenu_time_steps(cosenu_sim *s, int64_t nsteps, double *ms);
-/* Times each stage kernel separately over nsteps steps (eagerly launched,
+/* Times each launch of a step separately over nsteps steps (eagerly launched,
  * one event pair around each launch); ms_stage[4] receives the summed
- * milliseconds of stage 1..4.  Synchronises. */
+ * milliseconds of stages 1..4, or of the two fused stage pairs followed by two
+ * zeros.  Synchronises. */
 int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage);
 
 /* Picks seg_rows by timing candidate launch shapes on scratch buffers of
  * the handle's shape (the state is not modified); results are cached per
- * (scheme, precision, nv, nz bucket) for the process.  *seg_rows receives
+ * (scheme, precision, nv, nz bucket) and path (fused or not) for the process.  *seg_rows receives
  * the choice (may be NULL). */
 int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows);
 

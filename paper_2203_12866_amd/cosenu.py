@@ -70,6 +70,7 @@ class Info(ctypes.Structure):
         ("step", ctypes.c_int64), ("device_bytes", ctypes.c_size_t),
         ("seg_rows", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("v_chunks", ctypes.c_int32),
         ("blocks_per_stage", ctypes.c_int32), ("bytes_per_step", ctypes.c_double),
+        ("launches_per_step", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -112,6 +113,7 @@ def _lib():
             "cosenu_time_steps": (ctypes.c_int, [vp, i64, dp]),
             "cosenu_time_stages": (ctypes.c_int, [vp, i64, dp]),
             "cosenu_autotune": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
+            "cosenu_set_fusion": (ctypes.c_int, [vp, i32]),
             "cosenu_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "cosenu_last_error": (ctypes.c_char_p, [vp]),
             "cosenu_batch_create": (ctypes.c_int, [PP, i32, ctypes.POINTER(vp)]),
@@ -266,6 +268,10 @@ class Sim:
         ms = (ctypes.c_double * 4)()
         self._check(_lib().cosenu_time_stages(self._h, int(n), ms), "cosenu_time_stages")
         return list(ms)
+
+    def set_fusion(self, on: bool):
+        """Fused stage pairs where supported (default on); results are bitwise the same."""
+        self._check(_lib().cosenu_set_fusion(self._h, 1 if on else 0), "cosenu_set_fusion")
 
     def autotune(self) -> int:
         seg = ctypes.c_int32()

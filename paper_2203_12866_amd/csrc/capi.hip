@@ -115,6 +115,11 @@ double bytes_per_cell_step(int form) {
     return form == COSENU_FP64 ? 12.0 * 64.0 : 10.0 * 64.0 + 2.0 * 32.0;
 }
 
+double bytes_per_cell_step_fused(int form) {
+    // pair 0 reads y, writes Y3 and acc; pair 1 reads Y3, y and acc, writes y
+    return form == COSENU_FP64 ? 7.0 * 64.0 : 5.0 * 64.0 + 2.0 * 32.0;
+}
+
 void fill_desc_constants(const cosenu_params &p, InstDesc &d) {
     std::memset(&d, 0, sizeof d);
     d.nz = p.nz;
@@ -166,21 +171,21 @@ void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vect
 
 // Launch-shape cache shared by single instances and batches.
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, int> g_tune_cache;
+std::map<std::tuple<int, int, int, int, bool>, int> g_tune_cache;
 
-int tuned_seg(int scheme, int form, int nz, int nv) {
+int tuned_seg(int scheme, int form, int nz, int nv, bool pairs) {
     int bucket = 0;
     while ((1 << (bucket + 1)) <= nz) ++bucket;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_cache.find(std::make_tuple(scheme, form, nv, bucket));
+    auto it = g_tune_cache.find(std::make_tuple(scheme, form, nv, bucket, pairs));
     return it == g_tune_cache.end() ? 0 : it->second;
 }
 
-void store_tuned_seg(int scheme, int form, int nz, int nv, int seg) {
+void store_tuned_seg(int scheme, int form, int nz, int nv, bool pairs, int seg) {
     int bucket = 0;
     while ((1 << (bucket + 1)) <= nz) ++bucket;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[std::make_tuple(scheme, form, nv, bucket)] = seg;
+    g_tune_cache[std::make_tuple(scheme, form, nv, bucket, pairs)] = seg;
 }
 
 }  // namespace cosenu
@@ -192,8 +197,15 @@ struct cosenu_sim {
     int device = 0;
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
-    hipGraphExec_t g1 = nullptr, gN = nullptr;
+    // step graphs for a state held in buffer 0 or 1 (g1: one step, gN: gN_steps)
+    hipGraphExec_t g1[2] = {nullptr, nullptr}, gN[2] = {nullptr, nullptr};
     int gN_steps = 16;
+    // The fused pairs write the new state into the other of two buffers (the
+    // second fused pair still reads the old state on the halo rows of its
+    // segments, which neighbouring workgroups are rewriting); d.y is the buffer
+    // holding the current state, d.ya the other one.
+    double *state_buf[2] = {nullptr, nullptr};
+    int parity = 0;
     bool graphs_ok = false;
     double t = 0.0;
     int64_t step = 0;
@@ -203,8 +215,26 @@ struct cosenu_sim {
     double *diag_part = nullptr;   // [max tasks][kDiagQ]
     size_t diag_cap = 0;           // in tasks
     double *mom_out = nullptr;     // [nz][vchunks][8]
+    bool fusion_wanted = true;     // run fused stage pairs where the kernels support the shape
     std::string err;
 };
+
+namespace {
+bool fused(const cosenu_sim *s) { return s->fusion_wanted && pair_supported(s->d); }
+void point_state(InstDesc &d, const cosenu_sim *s, int p) {
+    d.y = s->state_buf[p];
+    d.ya = s->state_buf[1 - p];
+}
+void set_parity(cosenu_sim *s, int p) {
+    s->parity = p;
+    point_state(s->d, s, p);
+}
+int launches_per_step(const cosenu_sim *s) { return fused(s) ? 2 : 4; }
+// launch k of a step: a fused stage pair, or one single stage
+hipError_t launch_k(const cosenu_sim *s, int k, hipStream_t st) {
+    return fused(s) ? launch_pair(s->d, k, st) : launch_stage(s->d, k, blocks_for(s->d), st);
+}
+}  // namespace
 
 #define SIM_CHECK(s)                                   \
     do {                                               \
@@ -230,23 +260,36 @@ int sim_alloc(cosenu_sim *s, void **p, size_t bytes) {
 }
 
 void destroy_graphs(cosenu_sim *s) {
-    if (s->g1) (void)hipGraphExecDestroy(s->g1);
-    if (s->gN) (void)hipGraphExecDestroy(s->gN);
-    s->g1 = s->gN = nullptr;
+    for (int p = 0; p < 2; ++p) {
+        if (s->g1[p]) (void)hipGraphExecDestroy(s->g1[p]);
+        if (s->gN[p]) (void)hipGraphExecDestroy(s->gN[p]);
+        s->g1[p] = s->gN[p] = nullptr;
+    }
     s->graphs_ok = false;
 }
 
-int enqueue_stages(cosenu_sim *s, hipStream_t st, int nsteps) {
-    const int blocks = blocks_for(s->d);
-    for (int k = 0; k < nsteps; ++k)
-        for (int stage = 0; stage < 4; ++stage) HIPCHK(s, launch_stage(s->d, stage, blocks, st));
+// nsteps steps from a state in buffer p: four single stages per step (the
+// state stays in place), or two fused pairs (the state changes buffer)
+int enqueue_steps(cosenu_sim *s, hipStream_t st, int nsteps, int p) {
+    InstDesc d = s->d;
+    const bool pairs = fused(s);
+    for (int k = 0; k < nsteps; ++k) {
+        point_state(d, s, p);
+        if (pairs) {
+            HIPCHK(s, launch_pair(d, 0, st));
+            HIPCHK(s, launch_pair(d, 1, st));
+            p ^= 1;
+        } else {
+            for (int stage = 0; stage < 4; ++stage) HIPCHK(s, launch_stage(d, stage, blocks_for(d), st));
+        }
+    }
     return COSENU_OK;
 }
 
-int capture(cosenu_sim *s, int nsteps, hipGraphExec_t *out) {
+int capture(cosenu_sim *s, int nsteps, int p, hipGraphExec_t *out) {
     hipGraph_t graph = nullptr;
     HIPCHK(s, hipStreamBeginCapture(s->own_stream, hipStreamCaptureModeRelaxed));
-    int rc = enqueue_stages(s, s->own_stream, nsteps);
+    int rc = enqueue_steps(s, s->own_stream, nsteps, p);
     hipError_t e = hipStreamEndCapture(s->own_stream, &graph);
     if (rc != COSENU_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -267,10 +310,12 @@ int capture(cosenu_sim *s, int nsteps, hipGraphExec_t *out) {
 
 int build_graphs(cosenu_sim *s) {
     destroy_graphs(s);
-    int rc = capture(s, 1, &s->g1);
-    if (rc) return rc;
-    rc = capture(s, s->gN_steps, &s->gN);
-    if (rc) return rc;
+    for (int p = 0; p < 2; ++p) {
+        int rc = capture(s, 1, p, &s->g1[p]);
+        if (rc) return rc;
+        rc = capture(s, s->gN_steps, p, &s->gN[p]);
+        if (rc) return rc;
+    }
     s->graphs_ok = true;
     return COSENU_OK;
 }
@@ -377,7 +422,7 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) {
     s->stream = s->own_stream;
 
     fill_desc_constants(*p, s->d);
-    const int tuned = tuned_seg(p->scheme, p->precision, p->nz, p->nv);
+    const int tuned = tuned_seg(p->scheme, p->precision, p->nz, p->nv, fused(s));
     if (tuned > 0) set_shape(s->d, tuned);
 
     const int nz = p->nz, nv = p->nv;
@@ -387,11 +432,12 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) {
     void *ptr = nullptr;
     int rc;
     if ((rc = sim_alloc(s, &ptr, f64))) return fail(rc);
-    s->d.y = (double *)ptr;
+    s->state_buf[0] = (double *)ptr;
     if ((rc = sim_alloc(s, &ptr, f64))) return fail(rc);
     s->d.acc = (double *)ptr;
     if ((rc = sim_alloc(s, &ptr, f64))) return fail(rc);
-    s->d.ya = ptr;
+    s->state_buf[1] = (double *)ptr;
+    set_parity(s, 0);
     if ((rc = sim_alloc(s, &ptr, ybbytes))) return fail(rc);
     s->d.yb = ptr;
     const size_t mom_bytes = (size_t)nz * s->d.vchunks * 2 * kMomQ * sizeof(double);
@@ -445,9 +491,16 @@ int cosenu_step(cosenu_sim *s, int64_t nsteps) {
         int rc = build_graphs(s);
         if (rc) return rc;
     }
+    const bool pairs = fused(s);
     int64_t big = nsteps / s->gN_steps, rem = nsteps % s->gN_steps;
-    for (int64_t k = 0; k < big; ++k) HIPCHK(s, hipGraphLaunch(s->gN, s->stream));
-    for (int64_t k = 0; k < rem; ++k) HIPCHK(s, hipGraphLaunch(s->g1, s->stream));
+    for (int64_t k = 0; k < big; ++k) {
+        HIPCHK(s, hipGraphLaunch(s->gN[s->parity], s->stream));
+        if (pairs && (s->gN_steps & 1)) set_parity(s, s->parity ^ 1);
+    }
+    for (int64_t k = 0; k < rem; ++k) {
+        HIPCHK(s, hipGraphLaunch(s->g1[s->parity], s->stream));
+        if (pairs) set_parity(s, s->parity ^ 1);
+    }
     s->step += nsteps;
     s->t += (double)nsteps * s->d.dt;
     return COSENU_OK;
@@ -542,8 +595,10 @@ int cosenu_info(cosenu_sim *s, cosenu_info_t *out) {
     out->seg_rows = s->d.seg;
     out->lanes_per_row = 1 << s->d.lr_log2;
     out->v_chunks = s->d.vchunks;
-    out->blocks_per_stage = blocks_for(s->d);
-    out->bytes_per_step = bytes_per_cell_step(s->prm.precision) * (double)s->d.nz * s->d.nv;
+    out->blocks_per_stage = fused(s) ? s->d.nseg : blocks_for(s->d);
+    out->bytes_per_step = (fused(s) ? bytes_per_cell_step_fused(s->prm.precision) : bytes_per_cell_step(s->prm.precision)) *
+                          (double)s->d.nz * s->d.nv;
+    out->launches_per_step = launches_per_step(s);
     return COSENU_OK;
 }
 
@@ -560,10 +615,18 @@ int cosenu_set_seg_rows(cosenu_sim *s, int32_t seg_rows) {
     HIPCHK(s, hipStreamSynchronize(s->stream));
     int seg = seg_rows;
     if (seg == 0) {
-        seg = tuned_seg(s->prm.scheme, s->prm.precision, s->prm.nz, s->prm.nv);
+        seg = tuned_seg(s->prm.scheme, s->prm.precision, s->prm.nz, s->prm.nv, fused(s));
         if (seg == 0) seg = default_seg_rows(s->prm.nz, s->prm.nv);
     }
     set_shape(s->d, seg);
+    return build_graphs(s);
+}
+
+int cosenu_set_fusion(cosenu_sim *s, int32_t on) {
+    SIM_CHECK(s);
+    if (on != 0 && on != 1) return COSENU_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->fusion_wanted = on != 0;
     return build_graphs(s);
 }
 
@@ -593,16 +656,17 @@ int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage) {
     std::vector<hipEvent_t> ev(8);
     for (auto &e : ev) HIPCHK(s, hipEventCreate(&e));
     for (int k = 0; k < 4; ++k) ms_stage[k] = 0.0;
-    const int blocks = blocks_for(s->d);
+    const int nl = launches_per_step(s);
     int rc = COSENU_OK;
     for (int64_t n = 0; n < nsteps && !rc; ++n) {
-        for (int stage = 0; stage < 4; ++stage) {
+        for (int stage = 0; stage < nl; ++stage) {
             if (hipEventRecord(ev[2 * stage], s->stream) != hipSuccess) rc = COSENU_EDEVICE;
-            if (!rc && launch_stage(s->d, stage, blocks, s->stream) != hipSuccess) rc = COSENU_EDEVICE;
+            if (!rc && launch_k(s, stage, s->stream) != hipSuccess) rc = COSENU_EDEVICE;
             if (!rc && hipEventRecord(ev[2 * stage + 1], s->stream) != hipSuccess) rc = COSENU_EDEVICE;
         }
-        if (!rc && hipEventSynchronize(ev[7]) != hipSuccess) rc = COSENU_EDEVICE;
-        for (int stage = 0; stage < 4 && !rc; ++stage) {
+        if (!rc && nl == 2) set_parity(s, s->parity ^ 1);  // the fused pairs moved the state
+        if (!rc && hipEventSynchronize(ev[2 * nl - 1]) != hipSuccess) rc = COSENU_EDEVICE;
+        for (int stage = 0; stage < nl && !rc; ++stage) {
             float f = 0.f;
             if (hipEventElapsedTime(&f, ev[2 * stage], ev[2 * stage + 1]) != hipSuccess) rc = COSENU_EDEVICE;
             ms_stage[stage] += f;
@@ -622,7 +686,8 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
     SIM_CHECK(s);
     HIPCHK(s, hipStreamSynchronize(s->stream));
     // Stages 1..3 write only scratch (Y2, Y3, Y4, acc and the moments of
-    // those stage values), so timing them leaves the state untouched.
+    // those stage values), so timing them leaves the state untouched.  The
+    // tuned length is cached per (scheme, form, nv, nz bucket) and path.
     const int cands[] = {4, 8, 16, 32, 64, 128, 256};
     const InstDesc keep = s->d;
     int best = keep.seg;
@@ -633,12 +698,14 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
     for (int c : cands) {
         if (c > s->d.nz) break;
         set_shape(s->d, c);
-        const int blocks = blocks_for(s->d);
+        // single stages 1..3, or the first fused pair (stages 1 and 2), which
+        // both leave y and its moments untouched
+        const int ntime = fused(s) ? 1 : 3;
         double total = 0.0;
         bool ok = true;
         for (int rep = 0; rep < 4 && ok; ++rep) {
             ok = hipEventRecord(a, s->stream) == hipSuccess;
-            for (int stage = 0; stage < 3 && ok; ++stage) ok = launch_stage(s->d, stage, blocks, s->stream) == hipSuccess;
+            for (int stage = 0; stage < ntime && ok; ++stage) ok = launch_k(s, stage, s->stream) == hipSuccess;
             ok = ok && hipEventRecord(b, s->stream) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
             float f = 0.f;
             ok = ok && hipEventElapsedTime(&f, a, b) == hipSuccess;
@@ -660,7 +727,7 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
     (void)hipEventDestroy(b);
     s->d = keep;
     set_shape(s->d, best);
-    store_tuned_seg(s->prm.scheme, s->prm.precision, s->prm.nz, s->prm.nv, best);
+    store_tuned_seg(s->prm.scheme, s->prm.precision, s->prm.nz, s->prm.nv, fused(s), best);
     if (seg_rows) *seg_rows = best;
     return build_graphs(s);
 }

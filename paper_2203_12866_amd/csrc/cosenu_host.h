@@ -18,10 +18,12 @@ int lr_log2_for(int nv);
 int default_seg_rows(int nz, int nv);
 void set_shape(InstDesc &d, int seg);
 double bytes_per_cell_step(int form);
+double bytes_per_cell_step_fused(int form);
 void fill_desc_constants(const cosenu_params &p, InstDesc &d);
 void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vector<double> &part, double ee0n,
                       double ee0b, double t, int64_t step, cosenu_conserved_t *out);
-int tuned_seg(int scheme, int form, int nz, int nv);
-void store_tuned_seg(int scheme, int form, int nz, int nv, int seg);
+// tuned segment length per (scheme, form, nv, nz bucket) and path (fused stage pairs or single stages); 0 if none
+int tuned_seg(int scheme, int form, int nz, int nv, bool pairs);
+void store_tuned_seg(int scheme, int form, int nz, int nv, bool pairs, int seg);
 
 }  // namespace cosenu

@@ -66,6 +66,10 @@ hipError_t launch_batch_stage(const InstDesc *d_descs, const WaveTask *d_tasks, 
                               bool wave_rows, int stage, int blocks, hipStream_t st);
 // resident waves per CU of the batch stage kernels of one variant (the least over the four stages)
 int batch_waves_per_cu(int scheme, int form, bool wave_rows);
+// fused stage pairs (FD + KO, 32 < nv <= 256): pair 0 = stages 1 and 2, pair 1 = stages 3 and 4;
+// one workgroup of 2 vchunks waves per segment (d.nseg workgroups)
+bool pair_supported(const InstDesc &d);
+hipError_t launch_pair(const InstDesc &d, int pair, hipStream_t st);
 // ---- diagnostics (diag_kernels.hip) ----------------------------------------
 // per (segment, chunk) partials [nrowtasks][kDiagQ]:
 //   0..3 M0 (trace, x, y, z) summed g P - alpha gbar Pbar~ (without dz dv)

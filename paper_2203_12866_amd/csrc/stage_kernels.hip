@@ -182,8 +182,9 @@ __device__ __forceinline__ void write_row_moments(double m[kMomQ], int lr_log2, 
 // three DPP steps combine the eight partial sums of q (every lane of the
 // eight ends with the same total) and lane 8q writes it.  The association
 // order is fixed.  LDS operations of one wave complete in program order, so
-// the only ordering needed is the compiler's (signal fences).
-__device__ __forceinline__ void wave_row_moments(const double m[kMomQ], double *lds, int lane, gdouble *dst) {
+// the only ordering needed is the compiler's (signal fences).  Returns, in
+// lane 8q (q < 6), total q.
+__device__ __forceinline__ double wave_row_totals(const double m[kMomQ], double *lds, int lane) {
 #pragma unroll
     for (int q = 0; q < kMomQ; ++q) lds[q * kLdsQStride + lane] = m[q];
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -194,8 +195,12 @@ __device__ __forceinline__ void wave_row_moments(const double m[kMomQ], double *
     s += dpp_f64<0xB1, 0xF>(s);   // quad_perm [1,0,3,2]
     s += dpp_f64<0x4E, 0xF>(s);   // quad_perm [2,3,0,1]
     s += dpp_f64<0x141, 0xF>(s);  // row_half_mirror
-    if (part == 0 && qq < kMomQ) dst[qq] = s;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return s;
+}
+__device__ __forceinline__ void wave_row_moments(const double m[kMomQ], double *lds, int lane, gdouble *dst) {
+    const double s = wave_row_totals(m, lds, lane);
+    if ((lane & 7) == 0 && (lane >> 3) < kMomQ) dst[lane >> 3] = s;
 }
 
 // A register copy the compiler cannot coalesce with its source (the output
@@ -640,6 +645,272 @@ __device__ __forceinline__ void moments_group(const InstDesc &d, int task, int l
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused stage pairs for FD + KO with one row group per wave (32 < nv <= 256).  Pair 0 runs stages 1 and 2, pair 1 stages 3 and 4; the
+// intermediate stage value Z (Y2, or Y4) is never stored.
+//
+// One workgroup holds every (chunk, species) wave of one segment.  At step s
+// stage A produces Z row a = start + dir (s - 2) from its input X (y, or Y3),
+// and stage B produces row b = a - 2 dir of the pair's output from the last
+// four Z rows, kept in registers.  Stage B needs the angular moments of Z row
+// b over every chunk and species: each wave stores its six totals of row a in
+// a ring of LDS slots, one barrier per step makes them visible, and two steps
+// later every wave reads the slot lane-distributed and sums it exactly as the
+// unfused stage reads the moment partials from memory.  So every value, and
+// every moment partial written, is bitwise the one the four single stages
+// produce.  Z covers the segment and two rows on either side (its halo for
+// stage B), X four rows on either side.  Pair 1 writes the new state into the
+// second state buffer (d.ya); the host swaps the two after every step.
+//
+// Bytes per cell and step (8 components): FP64 form 192 + 256 = 448, FP32
+// form 160 + 224 = 384, against 768 and 704 for four single stages.
+// ---------------------------------------------------------------------------
+constexpr int kXchSlots = 4;  // LDS ring of Z moment totals: [slot][part][6]
+
+template <int FORM, int PAIR, bool REV>
+__device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int segi, int l, int dir, double *lds,
+                                          double *xch) {
+    constexpr bool XIN32 = FORM == 1 && PAIR == 1;  // X = Y3, stored in FP32 by the FP32 form
+    using T = typename std::conditional<FORM == 0, double, float>::type;
+    using TI = typename std::conditional<XIN32, float, double>::type;
+    constexpr int NC = 4, R = 4, CTR = 1, AH = 2;
+    const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
+    const int j = vc * kWave + l;
+    const bool lane_on = j < nv;
+    const int jl = lane_on ? j : nv - 1;
+    const int z0 = segi * d.seg, z1 = min(nz, z0 + d.seg);
+    const int nrows = z1 - z0;
+    const int start = dir > 0 ? z0 : z1 - 1;  // first row of stage B
+    const int nsteps = nrows + 4;
+
+    const double v = d.vel[jl];
+    const double gl = lane_on ? d.g[jl] : 0.0;
+    const double agl = lane_on ? d.agb[jl] : 0.0;
+    const double ca = sp ? -agl : gl, cb = sp ? agl : gl;
+    const double sgn = sp ? -1.0 : 1.0;
+    const T cv = (T)(v * (1.0 / 12.0));
+    const T ce = (T)d.ko16;
+    const size_t plane = d.ps;
+    const int cofs = sp * NC;
+    const gchar *xb = (const gchar *)(PAIR == 0 ? (const void *)d.y : d.yb) + (size_t)cofs * plane * sizeof(TI);
+    const gchar *yb8 = (const gchar *)d.y + (size_t)cofs * plane * 8;      // y (aux of stage 3)
+    const gchar *accb = (const gchar *)d.acc + (size_t)cofs * plane * 8;   // acc
+    constexpr uint32_t out_es = (PAIR == 0 && FORM == 1) ? 4 : 8;          // Y3 of the FP32 form is FP32
+    // pair 1 writes the new state into the other state buffer: its stage 3
+    // still reads the old state on the halo rows of the segment, which the
+    // neighbouring workgroups are rewriting
+    gchar *outb = (PAIR == 0 ? (gchar *)d.yb : (gchar *)d.ya) + (size_t)cofs * plane * out_es;
+    gchar *accw = (gchar *)d.acc + (size_t)cofs * plane * 8;
+    const size_t pin = plane * sizeof(TI), p64 = plane * 8, pout = plane * out_es;
+    const gdouble *m_in = (const gdouble *)(PAIR == 0 ? d.mom[0] : d.mom[2]);
+    gdouble *m_out = (gdouble *)(PAIR == 0 ? d.mom[2] : d.mom[0]);
+    const int nparts = 2 * vchunks;
+    const int part = vc * 2 + sp;
+    const int plog = 32 - __builtin_clz(nparts - 1);
+    const int pg = min(l / kPartLanes, 2), pp = min(l % kPartLanes, nparts - 1);
+    const bool p_on = l < 3 * kPartLanes && l % kPartLanes < nparts;
+    const int poff = pp * kMomQ + pg;
+
+    const double dzs = dir > 0 ? d.dz_inv : -d.dz_inv;
+    const double dt = d.dt, hdt = 0.5 * d.dt, dt6 = d.dt * (1.0 / 6.0);
+    const double third = 1.0 / 3.0;
+    const double mudv = d.mudv, h3vac = d.h3vac, hexvac = d.hexvac, lam = d.lam;
+
+    auto row_a = [&](int s) { return start + dir * (s - 2); };
+    auto load_x = [&](int row, TI (&dst)[NC]) {
+        const uint32_t off = (uint32_t)(row * nv + jl) * (uint32_t)sizeof(TI);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) dst[c] = ld<TI>(xb + (size_t)c * pin, off);
+    };
+    struct Buf {
+        TI nw[NC];     // X look-ahead row a + 2 dir
+        double pv[2];  // lane-distributed moment partials of X row a
+        double ya[NC]; // pair 1: y at row a (stage 3 combine)
+    };
+    auto issue = [&](int s, Buf &b) {
+        const int a = wrap_row(row_a(s), nz);
+        load_x(wrap_row(row_a(s) + dir * AH, nz), b.nw);
+        const int ar = __builtin_amdgcn_readfirstlane(a);
+        const gdouble *mp = m_in + (size_t)ar * nparts * kMomQ;
+        b.pv[0] = mp[poff];
+        b.pv[1] = mp[poff + 3];
+        if constexpr (PAIR == 1) {
+            const uint32_t offa = (uint32_t)(ar * nv + jl) * 8u;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) b.ya[c] = ld<double>(yb8 + (size_t)c * p64, offa);
+        }
+    };
+
+    TI xw[NC][R - 1];   // carried X rows a - dir, a, a + dir
+    double lag[NC];     // X row a - 2 dir (pair 0: y at the stage B row)
+    double zw[NC][R];   // Z rows a - 3 dir .. a (dir order)
+    T fA[NC], fB[NC];   // fluxes on the faces behind rows a and b
+
+    auto flux = [&](auto x) -> T {  // FD + KO interface flux from four window rows in dir order
+        return REV ? fd_ko_flux<T>(x(3), x(2), x(1), x(0), cv, ce) : fd_ko_flux<T>(x(0), x(1), x(2), x(3), cv, ce);
+    };
+    auto hamiltonian = [&](const double S[kMomQ], double &h3, double &hr, double &hi) {
+        const double A0 = S[0] - v * S[3];
+        const double A1 = S[1] - v * S[4];
+        const double A2 = S[2] - v * S[5];
+        h3 = h3vac + sgn * (lam + mudv * A0);
+        hr = hexvac + sgn * (mudv * A1);
+        hi = mudv * A2;
+    };
+
+    auto compute = [&](int s, const Buf &b) {
+        const int a = row_a(s);
+        // pair 1: acc at the stage B row, loaded here and used at the end of the step
+        double ab[NC];
+        if constexpr (PAIR == 1) {
+            const int br = s >= 4 ? a - 2 * dir : start;  // stage B row (in [z0, z1) from s = 4)
+            const uint32_t offb = (uint32_t)(br * nv + jl) * 8u;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) ab[c] = ld<double>(accb + (size_t)c * p64, offb);
+        }
+        // ---- stage A: Z row a
+        auto win = [&](int c, int m) -> TI { return m < R - 1 ? xw[c][m] : b.nw[c]; };
+        double adv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const T fn = flux([&](int m) -> T { return (T)win(c, m); });
+            adv[c] = ((double)fn - (double)fA[c]) * dzs;
+            fA[c] = fn;
+        }
+        double S[kMomQ];
+        {
+            const double pz[2] = {p_on ? b.pv[0] : 0.0, p_on ? b.pv[1] : 0.0};
+            sum_row_parts(pz, plog, S);
+        }
+        double h3, hr, hi, u[NC], kk[NC];
+        hamiltonian(S, h3, hr, hi);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) u[c] = (double)(T)win(c, CTR);
+        minus_i_commutator(h3, hr, hi, u[0], u[1], u[2], u[3], kk[0], kk[1], kk[2], kk[3]);
+        double z[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            kk[c] -= adv[c];
+            if constexpr (PAIR == 0) z[c] = (double)win(c, CTR) + hdt * kk[c];  // stage 1: Y2
+            else z[c] = b.ya[c] + dt * kk[c];                                   // stage 3: Y4
+        }
+        // slide X at the end of the step (the dropped row is kept: pair 0 needs
+        // y at the stage B row of the next step)
+        auto slide_x = [&]() {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                lag[c] = (double)xw[c][0];
+                xw[c][0] = xw[c][1];
+                xw[c][1] = xw[c][2];
+                xw[c][2] = fresh_copy(b.nw[c]);
+            }
+        };
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            zw[c][0] = zw[c][1];
+            zw[c][1] = zw[c][2];
+            zw[c][2] = zw[c][3];
+            zw[c][3] = z[c];
+        }
+        // moments of Z row a for stage B (rows of the segment only)
+        const bool a_in = s >= 2 && s < nrows + 2;
+        if (a_in) {
+            double o[NC], mt[kMomQ];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                o[c] = FORM == 1 ? (double)(float)z[c] : z[c];  // the next stage sees FP32 values
+                if (!lane_on) o[c] = 0.0;
+            }
+            species_moment_terms(o, ca, cb, v, mt);
+            const double t = wave_row_totals(mt, lds, l);
+            if ((l & 7) == 0 && (l >> 3) < kMomQ) xch[((s % kXchSlots) * nparts + part) * kMomQ + (l >> 3)] = t;
+        }
+        __syncthreads();
+        if (s == 3) {  // flux on the face behind the first stage B row, from Z rows start - 2 dir .. start + dir
+#pragma unroll
+            for (int c = 0; c < NC; ++c) fB[c] = flux([&](int m) -> T { return (T)zw[c][m]; });
+        }
+        if (s < 4) {
+            slide_x();
+            return;
+        }
+        // ---- stage B: output row b
+        const int brow = a - 2 * dir;
+        double SB[kMomQ];
+        {
+            const double *xs = xch + ((s - 2) % kXchSlots) * nparts * kMomQ;
+            const double pz[2] = {p_on ? xs[poff] : 0.0, p_on ? xs[poff + 3] : 0.0};
+            sum_row_parts(pz, plog, SB);
+        }
+        // Z window of row b: rows b - dir .. b + 2 dir = zw[0..3]
+        double advB[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const T fn = flux([&](int m) -> T { return (T)zw[c][m]; });
+            advB[c] = ((double)fn - (double)fB[c]) * dzs;
+            fB[c] = fn;
+        }
+        hamiltonian(SB, h3, hr, hi);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) u[c] = (double)(T)zw[c][1];
+        minus_i_commutator(h3, hr, hi, u[0], u[1], u[2], u[3], kk[0], kk[1], kk[2], kk[3]);
+        const uint32_t off64 = (uint32_t)(brow * nv + jl) * 8u;
+        const uint32_t offo = (uint32_t)(brow * nv + jl) * out_es;
+        double o[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            kk[c] -= advB[c];
+            const double zc = zw[c][1];  // exact Z at row b
+            if constexpr (PAIR == 0) {   // stage 2: Y3 and acc
+                o[c] = lag[c] + hdt * kk[c];
+                if (lane_on) st<double>(accw + (size_t)c * p64, off64, ((lag[c] + zc) + dt * kk[c]) * third);
+            } else {                     // stage 4: the new state
+                o[c] = (ab[c] + zc * third) + dt6 * kk[c];
+            }
+            if (lane_on) {
+                if constexpr (out_es == 8) st<double>(outb + (size_t)c * pout, offo, o[c]);
+                else st<float>(outb + (size_t)c * pout, offo, (float)o[c]);
+            }
+            if (FORM == 1) o[c] = (double)(float)o[c];
+            if (!lane_on) o[c] = 0.0;
+        }
+        double mt[kMomQ];
+        species_moment_terms(o, ca, cb, v, mt);
+        wave_row_moments(mt, lds, l, m_out + (((size_t)brow * vchunks + vc) * 2 + sp) * kMomQ);
+        slide_x();
+    };
+
+    // prologue: X rows a(0) - 2 dir .. a(0) + dir, then the loads of step 0,
+    // then the flux on the face behind row a(0)
+    const int a0 = row_a(0);
+    TI low[NC];
+    load_x(wrap_row(a0 - 2 * dir, nz), low);
+#pragma unroll
+    for (int m = 0; m < R - 1; ++m) {
+        TI tmp[NC];
+        load_x(wrap_row(a0 + dir * (m - CTR), nz), tmp);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xw[c][m] = tmp[c];
+    }
+    Buf bufA, bufB;
+    issue(0, bufA);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        fA[c] = flux([&](int m) -> T { return m == 0 ? (T)low[c] : (T)xw[c][m - 1]; });
+        lag[c] = 0.0;
+        fB[c] = T(0);
+#pragma unroll
+        for (int m = 0; m < R; ++m) zw[c][m] = 0.0;
+    }
+    for (int s = 0; s < nsteps; s += 2) {
+        if (s + 1 < nsteps) issue(s + 1, bufB);
+        compute(s, bufA);
+        if (s + 1 >= nsteps) break;
+        if (s + 2 < nsteps) issue(s + 2, bufA);
+        compute(s + 1, bufB);
+    }
+}
+
 // XCD-aware block order: the hardware deals workgroups round-robin to the 8
 // XCDs; renumber so that each XCD receives a contiguous range of tasks and
 // neighbouring segments (which share halo rows) meet in the same L2.  With
@@ -710,6 +981,21 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock, (kMinWavesPerSimd<SCHEME, WR
         else stage_group<SCHEME, FORM, STAGE, false>(d, t.task0 + (lane >> d.lr_log2), lane & ((1 << d.lr_log2) - 1),
                                                      nullptr);
     }
+}
+
+// Fused stage pairs: one workgroup per segment, one wave per (chunk, species).
+template <int FORM, int PAIR, int NW>
+__global__ __launch_bounds__(kWave *NW, 3) void pair_kernel(InstDesc d) {
+    extern __shared__ __align__(16) double pair_pool[];
+    const int nw = blockDim.x >> 6;  // 2 vchunks
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & (kWave - 1);
+    const int segi = xcd_block(blockIdx.x, gridDim.x, PAIR == 1);
+    double *lds = pair_pool + w * kLdsPerWave;
+    double *xch = pair_pool + nw * kLdsPerWave;
+    const int vc = w >> 1, sp = w & 1;
+    if (kAltDir && (segi & 1)) pair_body<FORM, PAIR, true>(d, vc, sp, segi, lane, -1, lds, xch);
+    else pair_body<FORM, PAIR, false>(d, vc, sp, segi, lane, 1, lds, xch);
 }
 
 }  // namespace
@@ -810,6 +1096,27 @@ int batch_waves_per_cu_w(int scheme, int form) {
 
 int batch_waves_per_cu(int scheme, int form, bool wave_rows) {
     return wave_rows ? batch_waves_per_cu_w<true>(scheme, form) : batch_waves_per_cu_w<false>(scheme, form);
+}
+
+bool pair_supported(const InstDesc &d) { return d.scheme == 0 && d.lr_log2 == 6 && 2 * d.vchunks <= 8; }
+
+namespace {
+template <int FORM, int PAIR>
+hipError_t launch_pair_t(const InstDesc &d, dim3 grid, dim3 block, size_t shm, hipStream_t st) {
+    const int W = (int)block.x / kWave;
+    if (W <= 4) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 4>), grid, block, shm, st, d);
+    else hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 8>), grid, block, shm, st, d);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_pair(const InstDesc &d, int pair, hipStream_t st) {
+    if (!pair_supported(d)) return hipErrorInvalidValue;
+    const int W = 2 * d.vchunks;
+    const size_t shm = (size_t)(W * kLdsPerWave + kXchSlots * W * kMomQ) * sizeof(double);
+    const dim3 grid(d.nseg), block(kWave * W);
+    if (d.form == 0) return pair == 0 ? launch_pair_t<0, 0>(d, grid, block, shm, st) : launch_pair_t<0, 1>(d, grid, block, shm, st);
+    return pair == 0 ? launch_pair_t<1, 0>(d, grid, block, shm, st) : launch_pair_t<1, 1>(d, grid, block, shm, st);
 }
 
 hipError_t launch_batch_stage(const InstDesc *d_descs, const WaveTask *d_tasks, int nwt, int scheme, int form,
