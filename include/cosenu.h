@@ -230,7 +230,7 @@ int cosenu_batch_info(cosenu_batch *b, int32_t i, cosenu_info_t *out);
 int cosenu_batch_time_steps(cosenu_batch *b, int64_t nsteps, double *ms);
 /* Batch autotuner: chooses the segment length of every kernel variant of the
  * batch (variant 2*scheme + (nv > 32)) by timing stages 1-3 of that variant
- * alone for seg in {4, 8, ..., 128}; every instance of a variant takes the same
+ * alone for seg in {4, 6, 8, 11, ..., 128} (about sqrt(2) apart); every instance of a variant takes the same
  * length (at most its nz).  Then rebuilds the task lists and re-captures the
  * step graphs.  States, clocks and results are unchanged (results do not
  * depend on the segment length).  seg_rows, if not NULL, receives 4 values

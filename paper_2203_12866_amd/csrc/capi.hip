@@ -688,7 +688,9 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
     // Stages 1..3 write only scratch (Y2, Y3, Y4, acc and the moments of
     // those stage values), so timing them leaves the state untouched.  The
     // tuned length is cached per (scheme, form, nv, nz bucket) and path.
-    const int cands[] = {4, 8, 16, 32, 64, 128, 256};
+    // segment lengths about sqrt(2) apart: the workgroup count of the fused pairs
+    // (one per segment) has to land just under a whole number of resident rounds
+    const int cands[] = {4, 6, 8, 11, 16, 22, 32, 45, 64, 90, 128, 181, 256};
     const InstDesc keep = s->d;
     int best = keep.seg;
     double best_ms = 1e300;
