@@ -758,16 +758,25 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
         hi = mudv * A2;
     };
 
-    auto compute = [&](int s, const Buf &b) {
-        const int a = row_a(s);
-        // pair 1: acc at the stage B row, loaded here and used at the end of the step
-        double ab[NC];
+    // pair 1: acc at the stage B row of step s, loaded at the end of step s - 1
+    // (one buffer: it is consumed at the end of its step, then refilled).  The
+    // FP64 form has no registers to spare for it across steps and loads it at
+    // the start of its own step instead.
+    constexpr bool ACC_AHEAD = FORM == 1;
+    double abn[NC];  // the carried buffer (FP32 form)
+    auto load_acc = [&](int s, double (&dst)[NC]) {
         if constexpr (PAIR == 1) {
-            const int br = s >= 4 ? a - 2 * dir : start;  // stage B row (in [z0, z1) from s = 4)
+            const int br = s >= 4 ? row_a(s) - 2 * dir : start;  // stage B row (in [z0, z1) from s = 4)
             const uint32_t offb = (uint32_t)(br * nv + jl) * 8u;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) ab[c] = ld<double>(accb + (size_t)c * p64, offb);
+            for (int c = 0; c < NC; ++c) dst[c] = ld<double>(accb + (size_t)c * p64, offb);
         }
+    };
+    auto compute = [&](int s, const Buf &b) {
+        const int a = row_a(s);
+        double abl[NC];
+        if (!ACC_AHEAD && s >= 4) load_acc(s, abl);
+        const double(&ab)[NC] = ACC_AHEAD ? abn : abl;
         // ---- stage A: Z row a
         auto win = [&](int c, int m) -> TI { return m < R - 1 ? xw[c][m] : b.nw[c]; };
         double adv[NC];
@@ -832,6 +841,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
         }
         if (s < 4) {
             slide_x();
+            if (ACC_AHEAD && s == 3) load_acc(4, abn);
             return;
         }
         // ---- stage B: output row b
@@ -878,6 +888,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
         species_moment_terms(o, ca, cb, v, mt);
         wave_row_moments(mt, lds, l, m_out + (((size_t)brow * vchunks + vc) * 2 + sp) * kMomQ);
         slide_x();
+        if (ACC_AHEAD && s + 1 < nsteps) load_acc(s + 1, abn);
     };
 
     // prologue: X rows a(0) - 2 dir .. a(0) + dir, then the loads of step 0,
