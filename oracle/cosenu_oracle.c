@@ -27,8 +27,11 @@
  *     states the inverse ratio, which would not produce the ELN crossing).
  *   - velocity bins are midpoints v_j = -1 + (j+1/2) dv and the velocity
  *     integral is the Riemann sum over them (Sec. 3, opening paragraph), for
- *     both schemes.
- *   - the angular distributions are normalised discretely: sum_j dv g_j = 1.
+ *     both schemes.  Sec. 3.1 also describes a vertex grid over [-1, 1] with
+ *     the trapezoid rule, and Simpson's rule; both are available as
+ *     alternatives (quad = 1, 2), with v_j = -1 + j dv, dv = 2/(nv-1), and
+ *     the rule's weights w_j in every velocity integral and sum.
+ *   - the angular distributions are normalised discretely: sum_j w_j g_j = 1.
  *   - Kreiss-Oliger: "d_t u -> d_t u + Q u" moves Q to the left-hand side, so
  *     du/dt = (rest) - Q u; this is the dissipative sign (Sec. 3.1).
  *   - WENO7 linear weights: the values listed after eq:f4s are in reversed
@@ -71,6 +74,8 @@ typedef struct {
     double weno_eps; /* WENO regulator (paper: about 1e-6)                   */
     const double *g_nu;
     const double *g_nubar;
+    int32_t quad;    /* velocity grid and rule: 0 midpoint bins + Riemann sum,
+                        1 vertex grid + trapezoid, 2 vertex grid + Simpson */
 } oracle_params;
 
 /* ------------------------------------------------------------------------ */
@@ -135,9 +140,27 @@ static mat2 density_matrix(const double *Y, int base, int nz, int nv, int z, int
 /* ------------------------------------------------------------------------ */
 /* Grid (Sec. 3, opening paragraph).                                          */
 /* ------------------------------------------------------------------------ */
-double oracle_velocity(int32_t nv, int32_t j) {
-    double dv = 2.0 / nv;
-    return -1.0 + (j + 0.5) * dv; /* each bin is represented by its midpoint */
+double oracle_velocity_q(int32_t nv, int32_t quad, int32_t j) {
+    if (quad == 0) {
+        double dv = 2.0 / nv;
+        return -1.0 + (j + 0.5) * dv; /* each bin is represented by its midpoint */
+    }
+    double dv = 2.0 / (nv - 1);       /* vertex grid: v_0 = -1, v_{nv-1} = +1 */
+    return -1.0 + j * dv;
+}
+
+double oracle_velocity(int32_t nv, int32_t j) { return oracle_velocity_q(nv, 0, j); }
+
+/* Quadrature weight of point j: the Riemann sum (dv), the composite trapezoid
+ * rule (dv, halved at both ends) or the composite Simpson rule (dv/3 times
+ * 1, 4, 2, 4, ..., 2, 4, 1; nv odd). */
+double oracle_vweight(int32_t nv, int32_t quad, int32_t j) {
+    if (quad == 0) return 2.0 / nv;
+    double dv = 2.0 / (nv - 1);
+    int end = (j == 0 || j == nv - 1);
+    if (quad == 1) return end ? 0.5 * dv : dv;
+    if (end) return dv / 3.0;
+    return (j % 2 == 1) ? 4.0 * dv / 3.0 : 2.0 * dv / 3.0;
 }
 
 double oracle_position(int32_t nz, double L, int32_t i) {
@@ -145,27 +168,31 @@ double oracle_position(int32_t nz, double L, int32_t i) {
     return -0.5 * L + (i + 0.5) * dz;
 }
 
-/* dt = C_CFL dz / max |v_z|, the maximum taken over the discrete bins. */
-double oracle_dt(int32_t nz, int32_t nv, double L, double cfl) {
+/* dt = C_CFL dz / max |v_z|, the maximum taken over the discrete grid. */
+double oracle_dt_q(int32_t nz, int32_t nv, int32_t quad, double L, double cfl) {
     double vmax = 0.0;
     for (int j = 0; j < nv; ++j) {
-        double a = fabs(oracle_velocity(nv, j));
+        double a = fabs(oracle_velocity_q(nv, quad, j));
         if (a > vmax) vmax = a;
     }
     return cfl * (L / nz) / vmax;
 }
 
+double oracle_dt(int32_t nz, int32_t nv, double L, double cfl) { return oracle_dt_q(nz, nv, 0, L, cfl); }
+
 /* g(v) proportional to exp(-(v-1)^2 / (2 sigma^2)), normalised so that the
- * Riemann sum over the bins is one (Sec. 5, the Gaussian angular family). */
-void oracle_angular_dist(int32_t nv, double sigma, double *g) {
-    double dv = 2.0 / nv, norm = 0.0;
+ * quadrature over the grid is one (Sec. 5, the Gaussian angular family). */
+void oracle_angular_dist_q(int32_t nv, int32_t quad, double sigma, double *g) {
+    double norm = 0.0;
     for (int j = 0; j < nv; ++j) {
-        double v = oracle_velocity(nv, j);
+        double v = oracle_velocity_q(nv, quad, j);
         g[j] = exp(-(v - 1.0) * (v - 1.0) / (2.0 * sigma * sigma));
-        norm += dv * g[j];
+        norm += oracle_vweight(nv, quad, j) * g[j];
     }
     for (int j = 0; j < nv; ++j) g[j] /= norm;
 }
+
+void oracle_angular_dist(int32_t nv, double sigma, double *g) { oracle_angular_dist_q(nv, 0, sigma, g); }
 
 /* Initial data of eqs:perts: a pure flavour state perturbed by eps(z) =
  * amp exp(-z^2/width), identical in every velocity bin.  The off-diagonal
@@ -320,7 +347,7 @@ static void fv_weno7_line(const double *u, double *out, int nz, size_t stride, d
 void oracle_rhs(const oracle_params *p, const double *Y, double *K) {
     const int nz = p->nz, nv = p->nv;
     const size_t plane = (size_t)nz * nv;
-    const double dz = p->L / nz, dv = 2.0 / nv;
+    const double dz = p->L / nz;
 
     /* H_vac = (omega/2) [[-cos 2theta, sin 2theta], [sin 2theta, cos 2theta]], same for nubar */
     mat2 Hvac = mat_zero();
@@ -336,12 +363,12 @@ void oracle_rhs(const oracle_params *p, const double *Y, double *K) {
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z) {
         for (int j = 0; j < nv; ++j) {
-            double vj = oracle_velocity(nv, j);
+            double vj = oracle_velocity_q(nv, p->quad, j);
             /* velocity integrals of eq:ham with rho -> g rho, rhobar -> gbar rhobar (Sec. 5) */
             mat2 S = mat_zero(), Sb = mat_zero();
             for (int l = 0; l < nv; ++l) {
-                double vl = oracle_velocity(nv, l);
-                double w = dv * (1.0 - vj * vl);
+                double vl = oracle_velocity_q(nv, p->quad, l);
+                double w = oracle_vweight(nv, p->quad, l) * (1.0 - vj * vl);
                 mat2 r = density_matrix(Y, 0, nz, nv, z, l);
                 mat2 rb = density_matrix(Y, 4, nz, nv, z, l);
                 mat2 term = mat_sub(mat_scale(r, p->g_nu[l]), mat_scale(mat_conj(rb), p->alpha * p->g_nubar[l]));
@@ -372,7 +399,7 @@ void oracle_rhs(const oracle_params *p, const double *Y, double *K) {
 #pragma omp for collapse(2) schedule(static)
         for (int c = 0; c < 8; ++c) {
             for (int j = 0; j < nv; ++j) {
-                double vj = oracle_velocity(nv, j);
+                double vj = oracle_velocity_q(nv, p->quad, j);
                 const double *u = Y + c * plane + j;
                 double *out = K + c * plane + j;
                 if (p->scheme == 0)
@@ -414,16 +441,16 @@ int oracle_rk4(const oracle_params *p, double *y, int64_t nsteps) {
 
 /* ------------------------------------------------------------------------ */
 /* Angular moments of D = g rho - alpha gbar rhobar^* per z row:              */
-/*   out[(z*2 + m)*4 + q],  m = 0: dv sum_j D_j,  m = 1: dv sum_j v_j D_j,    */
+/*   out[(z*2 + m)*4 + q],  m = 0: sum_j w_j D_j,  m = 1: sum_j w_j v_j D_j,  */
 /*   q = 0 D_ee, 1 D_xx, 2 Re D_ex, 3 Im D_ex.                                */
 /* ------------------------------------------------------------------------ */
 void oracle_moments(const oracle_params *p, const double *Y, double *out) {
     const int nz = p->nz, nv = p->nv;
-    const double dv = 2.0 / nv;
     for (int z = 0; z < nz; ++z) {
         double m[2][4] = {{0}};
         for (int j = 0; j < nv; ++j) {
-            double vj = oracle_velocity(nv, j);
+            double vj = oracle_velocity_q(nv, p->quad, j);
+            double dv = oracle_vweight(nv, p->quad, j);
             mat2 r = density_matrix(Y, 0, nz, nv, z, j);
             mat2 rb = density_matrix(Y, 4, nz, nv, z, j);
             mat2 D = mat_sub(mat_scale(r, p->g_nu[j]), mat_scale(mat_conj(rb), p->alpha * p->g_nubar[j]));
@@ -445,22 +472,24 @@ void oracle_moments(const oracle_params *p, const double *Y, double *out) {
 /* Polarisation vector: rho = (P0 + P . sigma)/2, so P = (2 Re rho_ex,        */
 /* -2 Im rho_ex, rho_ee - rho_xx).  For the antineutrino the matrix entering  */
 /* D is rhobar^*, whose vector is (2 Re rhob_ex, +2 Im rhob_ex, ...).         */
-/* out[0..3]  M0 = dz dv sum (g P - alpha gbar Pbar*) as (trace, x, y, z)     */
-/* out[4]     N_nu    = dz dv sum g Tr rho                                    */
-/* out[5]     N_nubar = dz dv sum gbar Tr rhobar                              */
+/* (w_j is the quadrature weight: dv for the midpoint bins)                   */
+/* out[0..3]  M0 = dz sum w (g P - alpha gbar Pbar*) as (trace, x, y, z)      */
+/* out[4]     N_nu    = dz sum w g Tr rho                                     */
+/* out[5]     N_nubar = dz sum w gbar Tr rhobar                               */
 /* out[6]     dP_max  = max over cells and species of | |P| - 1 |             */
-/* out[7]     <dP>    = sum g | |P_nu| - 1 | / sum g                          */
-/* out[8]     dz dv sum g rho_ee       out[9]  dz dv sum gbar rhobar_ee       */
+/* out[7]     <dP>    = sum w g | |P_nu| - 1 | / sum w g                      */
+/* out[8]     dz sum w g rho_ee        out[9]  dz sum w gbar rhobar_ee        */
 /* out[10]    B.M0 with B = (sin 2theta, 0, -cos 2theta)                      */
 /* out[11]    number of non-finite values in the state                        */
 /* ------------------------------------------------------------------------ */
 void oracle_diagnostics(const oracle_params *p, const double *Y, double *out) {
     const int nz = p->nz, nv = p->nv;
     const size_t plane = (size_t)nz * nv;
-    const double dz = p->L / nz, dv = 2.0 / nv, cell = dz * dv;
+    const double dz = p->L / nz;
     double M[4] = {0, 0, 0, 0}, Nn = 0, Nb = 0, dpmax = 0, dpw = 0, gw = 0, een = 0, eeb = 0, bad = 0;
     for (int z = 0; z < nz; ++z) {
         for (int j = 0; j < nv; ++j) {
+            const double wj = oracle_vweight(nv, p->quad, j), cell = dz * wj;
             size_t at = (size_t)z * nv + j;
             double y[8];
             for (int c = 0; c < 8; ++c) {
@@ -480,8 +509,8 @@ void oracle_diagnostics(const oracle_params *p, const double *Y, double *out) {
             double dpb = fabs(sqrt(Q1 * Q1 + Q2 * Q2 + Q3 * Q3) - 1.0);
             if (dpn > dpmax) dpmax = dpn;
             if (dpb > dpmax) dpmax = dpb;
-            dpw += g * dpn;
-            gw += g;
+            dpw += wj * g * dpn;
+            gw += wj * g;
             een += cell * g * y[0];
             eeb += cell * gb * y[4];
         }

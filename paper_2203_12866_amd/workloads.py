@@ -30,7 +30,8 @@ THETA_37 = 37.0 * math.pi / 180.0
 def _base(**kw) -> dict:
     w = dict(nz=512, nv=32, L=400.0, cfl=0.4, mu=1.0, omega=0.0, theta=THETA_37, lam=0.0,
              alpha=0.9, sigma_nu=0.6, sigma_nubar=0.5, pert_amp=1e-6, pert_width=50.0,
-             phase=0.0, scheme=FD_KO, precision=FP64, ko_eps=0.1, weno_eps=1e-6, steps=100)
+             phase=0.0, scheme=FD_KO, precision=FP64, ko_eps=0.1, weno_eps=1e-6, steps=100,
+             ko_order=2, quadrature=0)
     w.update(kw)
     return w
 

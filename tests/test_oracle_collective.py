@@ -99,11 +99,17 @@ def test_moments_and_diagnostics_are_the_stated_sums():
 # linear-regime growth (the full mu-coupled operator)
 # ---------------------------------------------------------------------------
 def _linear_prediction(S0, nz, nv, L, dt, steps, mu, alpha, g, gb, scheme, ko_eps):
+    return _linear_prediction_general(S0, np_velocities(nv), np.full(nv, 2.0 / nv), L, dt, steps, mu, alpha,
+                                      g, gb, scheme, ko_eps)
+
+
+def _linear_prediction_general(S0, v, w, L, dt, steps, mu, alpha, g, gb, scheme, ko_eps):
+    """The prediction for velocities v with quadrature weights w."""
     from tests.golden.fixtures import weno7_linear_coefficients
-    v = np_velocities(nv)
-    dv, dz = 2.0 / nv, L / nz
+    nz, nv = S0.shape
+    dz = L / nz
     G = g - alpha * gb
-    W = dv * (1.0 - np.outer(v, v))            # (1 - v_j v_l) dv
+    W = (1.0 - np.outer(v, v)) * w[None, :]    # (1 - v_j v_l) w_l
     Lam = mu * W @ G
     coup = 1j * mu * W * G[None, :]
     Shat = np.fft.fft(S0, axis=0)
