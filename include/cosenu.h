@@ -8,7 +8,7 @@
  *     (d/dt + v d/dz) rho    = -i [H,    rho   ],
  *     (d/dt + v d/dz) rhobar = -i [Hbar, rhobar],
  * with H = H_vac + H_m + H_nunu and Hbar = H_vac - H_m + Hbar_nunu (eq:ham),
- * on a periodic z grid times a grid of velocity bins v in [-1, 1] (Sec. 3),
+ * on a periodic z grid times a grid of velocities v in [-1, 1] (Sec. 3),
  * by the method of lines with classic fourth-order Runge-Kutta.  Advection is
  * either the fourth-order central finite difference with Kreiss-Oliger
  * dissipation (Sec. 3.1) or the finite-volume update eq:cell_av with WENO7
@@ -49,7 +49,7 @@ extern "C" {
 
 /* ---- discretisations and arithmetic forms -------------------------------- */
 enum cosenu_scheme {
-    COSENU_FD_KO = 0,    /* FD4 central advection + Kreiss-Oliger r = 2 (Sec. 3.1)      */
+    COSENU_FD_KO = 0,    /* FD4 central advection + Kreiss-Oliger of order r (Sec. 3.1)  */
     COSENU_FV_WENO7 = 1  /* finite volume eq:cell_av, WENO7 fluxes of f = v u (Sec. 3.2) */
 };
 enum cosenu_precision {
@@ -59,30 +59,46 @@ enum cosenu_precision {
                               the Runge-Kutta accumulation of the state in FP64           */
 };
 
+/* velocity grid and the rule of every velocity integral (Sec. 3 and 3.1) */
+enum cosenu_quadrature {
+    COSENU_QUAD_MIDPOINT = 0,  /* nv bins of width dv = 2/nv at their midpoints, Riemann sum  */
+    COSENU_QUAD_TRAPEZOID = 1, /* nv vertices v_j = -1 + j dv, dv = 2/(nv-1), trapezoid rule */
+    COSENU_QUAD_SIMPSON = 2    /* the same vertices (nv odd), composite Simpson rule          */
+};
+
 typedef struct cosenu_sim cosenu_sim;
 typedef struct cosenu_batch cosenu_batch;
 
 /* Problem description (Sec. 2, 3 and 5).  Units: 1/mu for t and z.
- *  nz, nv      number of z cells (periodic) and velocity bins; nz >= 5 for FD,
- *              nz >= 9 for WENO7; nv >= 2 (one bin would have max|v| = 0);
- *              nz * nv <= 2^29 (per-plane byte offsets are 32 bits).  Bins are midpoints
- *              v_j = -1 + (j + 1/2) * 2/nv; the velocity integral of eq:ham is
- *              the Riemann sum over them (Sec. 3).
+ *  nz, nv      number of z cells (periodic) and velocity points; nz >= 5 for FD
+ *              (>= 7 with ko_order 3), nz >= 9 for WENO7; nv >= 2 (one bin would
+ *              have max|v| = 0), odd for Simpson's rule; nz * nv <= 2^29 (per-plane
+ *              byte offsets are 32 bits).  The velocity grid and the rule of the
+ *              integral of eq:ham are set by quadrature.
  *  L           domain length; cells are centred at z_i = -L/2 + (i + 1/2) L/nz.
- *  cfl         dt = cfl * dz / max_j |v_j|  (Sec. 3); 0 < cfl <= 2.
+ *  cfl         dt = cfl * dz / max_j |v_j|  (Sec. 3); 0 < cfl <= 2.  max |v_j|
+ *              is 1 - 1/nv for the bins and 1 on a vertex grid.
  *  mu          self-interaction strength of eq:ham.
  *  omega,theta vacuum frequency and mixing angle (radians) of H_vac (Sec. 2).
  *  lambda      matter potential: H_m = diag(lambda, 0), Hbar_m = -diag(lambda, 0)
  *              (the paper removes H_m by a frame rotation, Sec. 2 footnote).
  *  alpha       n_nubar / n_nu (Sec. 5).
  *  sigma_nu, sigma_nubar  widths of g(v) ~ exp(-(v-1)^2 / 2 sigma^2), each
- *              normalised so that sum_j dv g_j = 1 (Sec. 5).
+ *              normalised so that sum_j w_j g_j = 1, w_j the quadrature
+ *              weights (Sec. 5).
  *  pert_amp, pert_width, phase   initial data eqs:perts with
  *              eps(z) = pert_amp * exp(-z^2 / pert_width), identical in every
  *              bin; rho_ex = eps/2 e^{i phase}, rhobar_ex = eps/2 e^{-i phase}
  *              (phase = 0 is the paper's data).
- *  ko_eps      Kreiss-Oliger strength (paper: 0.1), FD only.
- *  weno_eps    WENO regulator of eq:weight (paper: about 1e-6), WENO7 only.  */
+ *  ko_eps      Kreiss-Oliger strength (paper: 0.1), FD only; 0 switches the
+ *              dissipation off.
+ *  weno_eps    WENO regulator of eq:weight (paper: about 1e-6), WENO7 only.
+ *  ko_order    r of the Kreiss-Oliger operator eps (-1)^r dz^(2r-1) (D+)^r (D-)^r / 2^(2r)
+ *              (Sec. 3.1): 1, 2 (the paper's choice) or 3.  FD only, but
+ *              validated for both schemes.  Stage pairs are fused only for r <= 2.
+ *  quadrature  enum cosenu_quadrature (default COSENU_QUAD_MIDPOINT).
+ * Fields appended after weno_eps keep the offsets of the earlier ones;
+ * cosenu_params_default fills every field.  */
 typedef struct {
     int32_t nz, nv;
     int32_t scheme;    /* enum cosenu_scheme    */
@@ -92,15 +108,19 @@ typedef struct {
     double alpha, sigma_nu, sigma_nubar;
     double pert_amp, pert_width, phase;
     double ko_eps, weno_eps;
+    int32_t ko_order;   /* 1, 2 or 3                  */
+    int32_t quadrature; /* enum cosenu_quadrature     */
 } cosenu_params;
 
 /* Conserved quantities and error measures of Sec. 5, from the current state.
+ * Every sum over velocities carries the quadrature weight w_j (w_j = dv for
+ * the midpoint bins), written dv below.
  *  M0[4]     dz dv sum (g P - alpha gbar Pbar~) as (trace, x, y, z) where
  *            rho = (P0 + P.sigma)/2 and Pbar~ is the vector of rhobar^*; M0[3]
  *            is the net lepton number of Sec. 5.
  *  N_nu, N_nubar   dz dv sum g Tr rho, dz dv sum gbar Tr rhobar.
  *  dP_max    max over cells and species of | |P| - 1 |.
- *  dP_mean   sum g | |P_nu| - 1 | / sum g (g-weighted mean over all cells).
+ *  dP_mean   sum dv g | |P_nu| - 1 | / sum dv g (g-weighted mean over all cells).
  *  ee_nu, ee_nubar   dz dv sum g rho_ee, dz dv sum gbar rhobar_ee.
  *  Pee_nu, Pee_nubar survival probabilities: ee_* divided by its value at the
  *            last cosenu_create / cosenu_set_state (Sec. 4.2, taken g-weighted).
@@ -120,7 +140,7 @@ typedef struct {
 
 /* Read-only facts about a handle. */
 typedef struct {
-    double dt, dz, dv, t;
+    double dt, dz, dv, t;    /* dv: spacing of the velocity grid             */
     int64_t step;
     size_t device_bytes;     /* device memory owned by the handle              */
     int32_t seg_rows;        /* z rows marched by one lane group (launch shape) */
@@ -134,7 +154,8 @@ typedef struct {
 /* Fills *p with the paper's fiducial values (Sec. 5): nz = 512, nv = 32,
  * L = 400, cfl = 0.4, mu = 1, omega = lambda = 0, theta = 37 deg,
  * alpha = 0.9, sigma = 0.6 / 0.5, eps(z) = 1e-6 exp(-z^2/50), FD + KO with
- * ko_eps = 0.1, weno_eps = 1e-6, FP64.  Returns COSENU_EINVAL if p is NULL. */
+ * ko_eps = 0.1, ko_order = 2, weno_eps = 1e-6, midpoint bins, FP64.
+ * Returns COSENU_EINVAL if p is NULL. */
 int cosenu_params_default(cosenu_params *p);
 
 /* Validates *p, allocates the device state on the current HIP device,
@@ -229,11 +250,12 @@ int cosenu_batch_conserved(cosenu_batch *b, int32_t i, cosenu_conserved_t *out);
 int cosenu_batch_info(cosenu_batch *b, int32_t i, cosenu_info_t *out);
 int cosenu_batch_time_steps(cosenu_batch *b, int64_t nsteps, double *ms);
 /* Batch autotuner: chooses the segment length of every kernel variant of the
- * batch (variant 2*scheme + (nv > 32)) by timing stages 1-3 of that variant
+ * batch (variant 2*k + (nv > 32), k = 0 FD with ko_order <= 2, 1 WENO7, 2 FD
+ * with ko_order 3) by timing stages 1-3 of that variant
  * alone for seg in {4, 6, 8, 11, ..., 128} (about sqrt(2) apart); every instance of a variant takes the same
  * length (at most its nz).  Then rebuilds the task lists and re-captures the
  * step graphs.  States, clocks and results are unchanged (results do not
- * depend on the segment length).  seg_rows, if not NULL, receives 4 values
+ * depend on the segment length).  seg_rows, if not NULL, receives 6 values
  * (0 for variants absent from the batch).  Synchronises the handle's stream. */
 int cosenu_batch_autotune(cosenu_batch *b, int32_t *seg_rows);
 const char *cosenu_batch_last_error(const cosenu_batch *b);

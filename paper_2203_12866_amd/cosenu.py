@@ -21,6 +21,9 @@ FD_KO = 0
 FV_WENO7 = 1
 FP64 = 0
 FP32_ACC64 = 1
+QUAD_MIDPOINT = 0
+QUAD_TRAPEZOID = 1
+QUAD_SIMPSON = 2
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
 
@@ -43,6 +46,7 @@ class Params(ctypes.Structure):
         ("alpha", ctypes.c_double), ("sigma_nu", ctypes.c_double), ("sigma_nubar", ctypes.c_double),
         ("pert_amp", ctypes.c_double), ("pert_width", ctypes.c_double), ("phase", ctypes.c_double),
         ("ko_eps", ctypes.c_double), ("weno_eps", ctypes.c_double),
+        ("ko_order", ctypes.c_int32), ("quadrature", ctypes.c_int32),
     ]
 
 
@@ -354,7 +358,8 @@ class Batch:
         return ms.value
 
     def autotune(self) -> list:
-        """Segment length per kernel variant (2*scheme + (nv > 32)); 0 where absent."""
-        segs = (ctypes.c_int32 * 4)()
+        """Segment length per kernel variant 2*k + (nv > 32), k = 0 FD (KO r <= 2),
+        1 WENO7, 2 FD (KO r = 3); 0 where absent."""
+        segs = (ctypes.c_int32 * 6)()
         self._check(_lib().cosenu_batch_autotune(self._h, segs), "cosenu_batch_autotune")
         return list(segs)

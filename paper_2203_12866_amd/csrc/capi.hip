@@ -36,12 +36,17 @@ std::string validate_params(const cosenu_params &p) {
     auto fin = [](double x) { return std::isfinite(x); };
     if (p.scheme != COSENU_FD_KO && p.scheme != COSENU_FV_WENO7) return "scheme must be COSENU_FD_KO or COSENU_FV_WENO7";
     if (p.precision != COSENU_FP64 && p.precision != COSENU_FP32_ACC64) return "precision must be COSENU_FP64 or COSENU_FP32_ACC64";
-    const int nzmin = p.scheme == COSENU_FD_KO ? 5 : 9;
+    if (p.ko_order < 1 || p.ko_order > 3) return "ko_order must be 1, 2 or 3";
+    if (p.quadrature != COSENU_QUAD_MIDPOINT && p.quadrature != COSENU_QUAD_TRAPEZOID &&
+        p.quadrature != COSENU_QUAD_SIMPSON)
+        return "quadrature must be COSENU_QUAD_MIDPOINT, COSENU_QUAD_TRAPEZOID or COSENU_QUAD_SIMPSON";
+    const int nzmin = p.scheme == COSENU_FD_KO ? std::max(5, 2 * p.ko_order + 1) : 9;
     if (p.nz < nzmin) {
         snprintf(buf, sizeof buf, "nz = %d is below the stencil width (%d)", p.nz, nzmin);
         return buf;
     }
     if (p.nv < 2) return "nv must be >= 2 (with one bin max|v| = 0 and dt is undefined)";
+    if (p.quadrature == COSENU_QUAD_SIMPSON && p.nv % 2 == 0) return "Simpson's rule needs an odd nv";
     if ((double)p.nz * (double)p.nv > (double)(1u << 29)) return "nz * nv above 2^29 cells (32-bit byte offsets per plane)";
     if (!(fin(p.L) && p.L > 0)) return "L must be finite and > 0";
     if (!(fin(p.cfl) && p.cfl > 0 && p.cfl <= 2.0)) return "cfl must be in (0, 2]";
@@ -56,30 +61,70 @@ std::string validate_params(const cosenu_params &p) {
     return "";
 }
 
-// Bin midpoints v_j = -1 + (j + 1/2) dv (Sec. 3).
-std::vector<double> bin_velocities(int nv) {
+// Velocity grid spacing: bins of width 2/nv, or nv vertices spanning [-1, 1].
+double grid_dv(int nv, int quad) { return quad == COSENU_QUAD_MIDPOINT ? 2.0 / nv : 2.0 / (nv - 1); }
+
+// Bin midpoints v_j = -1 + (j + 1/2) dv (Sec. 3), or vertices v_j = -1 + j dv
+// (Sec. 3.1).
+std::vector<double> bin_velocities(int nv, int quad) {
     std::vector<double> v(nv);
-    const double dv = 2.0 / nv;
-    for (int j = 0; j < nv; ++j) v[j] = -1.0 + (j + 0.5) * dv;
+    const double dv = grid_dv(nv, quad);
+    const double first = quad == COSENU_QUAD_MIDPOINT ? 0.5 : 0.0;
+    for (int j = 0; j < nv; ++j) v[j] = -1.0 + (j + first) * dv;
     return v;
 }
 
-// g(v) ~ exp(-(v-1)^2 / 2 sigma^2) with sum_j dv g_j = 1 (Sec. 5).
-std::vector<double> gaussian_distribution(int nv, double sigma) {
-    std::vector<double> v = bin_velocities(nv), g(nv);
-    const double dv = 2.0 / nv;
+// Quadrature weights of the velocity integral (Sec. 3 and 3.1): dv per bin
+// (Riemann sum), the composite trapezoid rule (ends halved) or the composite
+// Simpson rule (dv/3 times 1, 4, 2, 4, ..., 4, 1).
+std::vector<double> quadrature_weights(int nv, int quad) {
+    const double dv = grid_dv(nv, quad);
+    std::vector<double> w(nv, dv);
+    if (quad == COSENU_QUAD_TRAPEZOID) {
+        w[0] = w[nv - 1] = 0.5 * dv;
+    } else if (quad == COSENU_QUAD_SIMPSON) {
+        for (int j = 0; j < nv; ++j) w[j] = (j == 0 || j == nv - 1) ? dv / 3.0 : (j % 2 ? 4.0 : 2.0) * dv / 3.0;
+    }
+    return w;
+}
+
+// g(v) ~ exp(-(v-1)^2 / 2 sigma^2) with sum_j w_j g_j = 1 (Sec. 5).
+std::vector<double> gaussian_distribution(int nv, int quad, double sigma) {
+    const std::vector<double> v = bin_velocities(nv, quad), w = quadrature_weights(nv, quad);
+    std::vector<double> g(nv);
     double s = 0.0;
     for (int j = 0; j < nv; ++j) {
         g[j] = std::exp(-(v[j] - 1.0) * (v[j] - 1.0) / (2.0 * sigma * sigma));
-        s += g[j] * dv;
+        s += g[j] * w[j];
     }
     for (int j = 0; j < nv; ++j) g[j] /= s;
     return g;
 }
 
+// Per-point constants as the kernels read them, [4][nv]: v_j, then g_j, gbar_j
+// and alpha gbar_j, each times w_j / dv.  The kernels form every velocity
+// integral as dv times a plain sum over the grid, so the rule's weights
+// travel inside the distributions (a factor of exactly one for the bins).
+std::vector<double> bin_constants(const cosenu_params &p) {
+    const int nv = p.nv, quad = p.quadrature;
+    const std::vector<double> v = bin_velocities(nv, quad), w = quadrature_weights(nv, quad);
+    const std::vector<double> g = gaussian_distribution(nv, quad, p.sigma_nu);
+    const std::vector<double> gb = gaussian_distribution(nv, quad, p.sigma_nubar);
+    const double dv = grid_dv(nv, quad);
+    std::vector<double> c(4 * (size_t)nv);
+    for (int j = 0; j < nv; ++j) {
+        const double f = quad == COSENU_QUAD_MIDPOINT ? 1.0 : w[j] / dv;
+        c[j] = v[j];
+        c[nv + j] = g[j] * f;
+        c[2 * nv + j] = gb[j] * f;
+        c[3 * nv + j] = p.alpha * (gb[j] * f);
+    }
+    return c;
+}
+
 double time_step(const cosenu_params &p) {
-    const double dv = 2.0 / p.nv;
-    const double vmax = 1.0 - 0.5 * dv;  // largest |midpoint|
+    // largest |v| over the grid: the outer midpoint, or 1 on a vertex grid
+    const double vmax = p.quadrature == COSENU_QUAD_MIDPOINT ? 1.0 - 0.5 * (2.0 / p.nv) : 1.0;
     return p.cfl * (p.L / p.nz) / vmax;
 }
 
@@ -124,18 +169,32 @@ void fill_desc_constants(const cosenu_params &p, InstDesc &d) {
     std::memset(&d, 0, sizeof d);
     d.nz = p.nz;
     d.nv = p.nv;
-    d.scheme = p.scheme;
+    // kernel variant: FD with the 4-row stencil (KO r = 1, 2), WENO7, FD with
+    // the 6-row stencil (KO r = 3)
+    d.scheme = p.scheme == COSENU_FD_KO && p.ko_order == 3 ? 2 : p.scheme;
     d.form = p.precision;
     d.lr_log2 = lr_log2_for(p.nv);
     d.vchunks = p.nv > kWave ? (p.nv + kWave - 1) / kWave : 1;
     d.dz_inv = p.nz / p.L;
     d.dt = time_step(p);
-    d.dv = 2.0 / p.nv;
+    d.dv = grid_dv(p.nv, p.quadrature);
     d.mudv = p.mu * d.dv;
     d.h3vac = -p.omega * std::cos(2.0 * p.theta);
     d.hexvac = 0.5 * p.omega * std::sin(2.0 * p.theta);
     d.lam = p.lambda;
-    d.ko16 = p.ko_eps / 16.0;
+    // Kreiss-Oliger flux -(-1)^r (eps / 2^(2r)) (delta^(2r-1) u)_{i+1/2} (Sec. 3.1),
+    // written as ko[0] (u_i - u_{i+1}) + ko[1] (u_{i+2} - u_{i-1}) + ko[2] (u_{i-2} - u_{i+3})
+    const double e = p.ko_eps;
+    if (p.ko_order == 1) {
+        d.ko[0] = e / 4.0;
+    } else if (p.ko_order == 2) {
+        d.ko[0] = 3.0 * e / 16.0;
+        d.ko[1] = e / 16.0;
+    } else {
+        d.ko[0] = 10.0 * e / 64.0;
+        d.ko[1] = 5.0 * e / 64.0;
+        d.ko[2] = e / 64.0;
+    }
     d.weno_eps = p.weno_eps;
     d.ps = (size_t)p.nz * p.nv + kPlanePad;
     set_shape(d, default_seg_rows(p.nz, p.nv));
@@ -393,6 +452,8 @@ int cosenu_params_default(cosenu_params *p) {
     p->phase = 0.0;
     p->ko_eps = 0.1;
     p->weno_eps = 1e-6;
+    p->ko_order = 2;
+    p->quadrature = COSENU_QUAD_MIDPOINT;
     return COSENU_OK;
 }
 
@@ -422,7 +483,7 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) {
     s->stream = s->own_stream;
 
     fill_desc_constants(*p, s->d);
-    const int tuned = tuned_seg(p->scheme, p->precision, p->nz, p->nv, fused(s));
+    const int tuned = tuned_seg(s->d.scheme, p->precision, p->nz, p->nv, fused(s));
     if (tuned > 0) set_shape(s->d, tuned);
 
     const int nz = p->nz, nv = p->nv;
@@ -446,18 +507,9 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) {
         s->d.mom[k] = (double *)ptr;
     }
     // per-bin constants
-    const std::vector<double> vel = bin_velocities(nv);
-    const std::vector<double> g = gaussian_distribution(nv, p->sigma_nu);
-    const std::vector<double> gb = gaussian_distribution(nv, p->sigma_nubar);
-    std::vector<double> agb(nv);
-    for (int j = 0; j < nv; ++j) agb[j] = p->alpha * gb[j];
+    const std::vector<double> hostc = bin_constants(*p);
     double *consts = nullptr;
-    if ((rc = sim_alloc(s, (void **)&consts, 4 * nv * sizeof(double)))) return fail(rc);
-    std::vector<double> hostc(4 * (size_t)nv);
-    std::copy(vel.begin(), vel.end(), hostc.begin());
-    std::copy(g.begin(), g.end(), hostc.begin() + nv);
-    std::copy(gb.begin(), gb.end(), hostc.begin() + 2 * nv);
-    std::copy(agb.begin(), agb.end(), hostc.begin() + 3 * nv);
+    if ((rc = sim_alloc(s, (void **)&consts, hostc.size() * sizeof(double)))) return fail(rc);
     if (hipMemcpy(consts, hostc.data(), hostc.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         return fail(COSENU_EDEVICE);
     s->d.vel = consts;
@@ -615,7 +667,7 @@ int cosenu_set_seg_rows(cosenu_sim *s, int32_t seg_rows) {
     HIPCHK(s, hipStreamSynchronize(s->stream));
     int seg = seg_rows;
     if (seg == 0) {
-        seg = tuned_seg(s->prm.scheme, s->prm.precision, s->prm.nz, s->prm.nv, fused(s));
+        seg = tuned_seg(s->d.scheme, s->prm.precision, s->prm.nz, s->prm.nv, fused(s));
         if (seg == 0) seg = default_seg_rows(s->prm.nz, s->prm.nv);
     }
     set_shape(s->d, seg);
@@ -729,7 +781,7 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
     (void)hipEventDestroy(b);
     s->d = keep;
     set_shape(s->d, best);
-    store_tuned_seg(s->prm.scheme, s->prm.precision, s->prm.nz, s->prm.nv, fused(s), best);
+    store_tuned_seg(s->d.scheme, s->prm.precision, s->prm.nz, s->prm.nv, fused(s), best);
     if (seg_rows) *seg_rows = best;
     return build_graphs(s);
 }

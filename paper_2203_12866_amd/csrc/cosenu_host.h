@@ -11,8 +11,11 @@ namespace cosenu {
 
 const char *strerror_code(int code);
 std::string validate_params(const cosenu_params &p);
-std::vector<double> bin_velocities(int nv);
-std::vector<double> gaussian_distribution(int nv, double sigma);
+double grid_dv(int nv, int quad);
+std::vector<double> bin_velocities(int nv, int quad);
+std::vector<double> quadrature_weights(int nv, int quad);
+std::vector<double> gaussian_distribution(int nv, int quad, double sigma);
+std::vector<double> bin_constants(const cosenu_params &p);
 double time_step(const cosenu_params &p);
 int lr_log2_for(int nv);
 int default_seg_rows(int nz, int nv);
@@ -22,7 +25,7 @@ double bytes_per_cell_step_fused(int form);
 void fill_desc_constants(const cosenu_params &p, InstDesc &d);
 void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vector<double> &part, double ee0n,
                       double ee0b, double t, int64_t step, cosenu_conserved_t *out);
-// tuned segment length per (scheme, form, nv, nz bucket) and path (fused stage pairs or single stages); 0 if none
+// tuned segment length per (kernel variant, form, nv, nz bucket) and path (fused stage pairs or single stages); 0 if none
 int tuned_seg(int scheme, int form, int nz, int nv, bool pairs);
 void store_tuned_seg(int scheme, int form, int nz, int nv, bool pairs, int seg);
 

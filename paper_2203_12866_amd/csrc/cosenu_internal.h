@@ -22,7 +22,8 @@ constexpr int kLdsPerWave = 8 * kLdsQStride;  // LDS doubles per wave (6 quantit
 // the single-instance kernels and stored in device memory for the batch.
 struct InstDesc {
     int32_t nz, nv;
-    int32_t scheme, form;
+    int32_t scheme;    // kernel variant: 0 FD (KO r = 1, 2), 1 WENO7, 2 FD (KO r = 3)
+    int32_t form;
     int32_t lr_log2;   // lanes per row group = 1 << lr_log2 (<= 64)
     int32_t vchunks;   // 64-bin chunks per row (1 when nv <= 64); = moment parts per row
     int32_t seg;       // rows per lane group
@@ -36,14 +37,14 @@ struct InstDesc {
     double h3vac;      // (H_vac)_ee - (H_vac)_xx = -omega cos 2theta
     double hexvac;     // (H_vac)_ex = omega/2 sin 2theta
     double lam;        // matter potential
-    double ko16;       // ko_eps / 16
+    double ko[3];      // Kreiss-Oliger flux coefficients of u_i - u_{i+1}, u_{i+2} - u_{i-1}, u_{i-2} - u_{i+3}
     double weno_eps;
     double dv;
     size_t ps;         // plane stride in elements: nz * nv + kPlanePad
-    const double *g;   // g_nu per bin                       [nv]
-    const double *gb;  // g_nubar per bin                    [nv]
-    const double *agb; // alpha * g_nubar per bin            [nv]
-    const double *vel; // bin midpoints                      [nv]
+    const double *g;   // g_nu per point times w_j / dv         [nv]
+    const double *gb;  // g_nubar per point times w_j / dv      [nv]
+    const double *agb; // alpha * gb                            [nv]
+    const double *vel; // velocity grid                         [nv]
     double *y;         // state, FP64                        [8][ps], plane = [nz][nv]
     double *acc;       // RK4 accumulator, FP64              [8][nz][nv]
     void *ya;          // Y2 / Y4 stage values, FP64         [8][nz][nv]

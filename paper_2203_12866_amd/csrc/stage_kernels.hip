@@ -76,15 +76,27 @@ __device__ __forceinline__ double group_sum(double x, int lr_log2) {
     return x;
 }
 
-// Interface flux at i+1/2 whose difference gives, for cell i,
-//   v (u_{i-2} - 8u_{i-1} + 8u_{i+1} - u_{i+2}) / 12  +  eps/16 (u_{i-2} - 4u_{i-1} + 6u_i - 4u_{i+1} + u_{i+2}),
-// i.e. dz times the FD4 central derivative term plus the Kreiss-Oliger r = 2
-// term of Sec. 3.1 (cv = v/12, ce = eps/16).
+// Interface flux at i+1/2 whose difference gives, for cell i, dz times the
+// FD4 central derivative term v (u_{i-2} - 8u_{i-1} + 8u_{i+1} - u_{i+2}) / 12
+// plus the Kreiss-Oliger term Q u of Sec. 3.1.  Q u = -(-1)^r eps/2^(2r)
+// delta^(2r) u / dz is the difference of the flux -(-1)^r eps/2^(2r)
+// (delta^(2r-1) u)_{i+1/2}: k0 (u_i - u_{i+1}) + k1 (u_{i+2} - u_{i-1}) with
+// k = (eps/4, 0) for r = 1 and (3 eps/16, eps/16) for r = 2 (cv = v/12).
 template <typename T>
-__device__ __forceinline__ T fd_ko_flux(T um1, T u0, T up1, T up2, T cv, T ce) {
+__device__ __forceinline__ T fd_ko_flux(T um1, T u0, T up1, T up2, T cv, T k0, T k1) {
     const T s_in = u0 + up1, s_out = um1 + up2;
     const T d_in = u0 - up1, d_out = up2 - um1;
-    return cv * (T(7) * s_in - s_out) + ce * (T(3) * d_in + d_out);
+    return cv * (T(7) * s_in - s_out) + (k0 * d_in + k1 * d_out);
+}
+
+// The same for r = 3, from six rows i-2..i+3: the KO flux is
+// k0 (u_i - u_{i+1}) + k1 (u_{i+2} - u_{i-1}) + k2 (u_{i-2} - u_{i+3}) with
+// k = (10, 5, 1) eps/64.
+template <typename T>
+__device__ __forceinline__ T fd_ko3_flux(T um2, T um1, T u0, T up1, T up2, T up3, T cv, T k0, T k1, T k2) {
+    const T s_in = u0 + up1, s_out = um1 + up2;
+    const T d_in = u0 - up1, d_mid = up2 - um1, d_out = um2 - up3;
+    return cv * (T(7) * s_in - s_out) + ((k0 * d_in + k1 * d_mid) + k2 * d_out);
 }
 
 // Normalised WENO combination sum_r w_r q_r / sum_r w_r with w_r = d_r / s_r,
@@ -252,7 +264,8 @@ __device__ __forceinline__ void species_moment_terms(const double o[4], double c
 }
 
 // Interface flux from the R window rows around it (FD: rows i-1..i+2 of the
-// interface i+1/2, WENO7: rows i-3..i+4), in window order.
+// interface i+1/2, or i-2..i+3 for KO r = 3; WENO7: rows i-3..i+4), in
+// window order.
 // WENO7 reconstructs f = v u.  Scaling eps by 1/v^2 makes it homogeneous of
 // degree one in f, WENO7(v u; eps) = v WENO7(u; eps / v^2), so the products
 // v u drop out (epsv is eps / v^2, or eps for v = 0, where the flux is 0).
@@ -264,9 +277,11 @@ __device__ __forceinline__ void species_moment_terms(const double o[4], double c
 // elements of an array would be lowered to an indexed read.
 template <int SCHEME, bool MIX, typename T>
 __device__ __forceinline__ T interface_flux(T u0, T u1, T u2, T u3, T u4, T u5, T u6, T u7, T tv, bool vpos, T cv,
-                                            T ce, T epsv) {
+                                            const T (&ko)[3], T epsv) {
     if constexpr (SCHEME == 0) {
-        return fd_ko_flux<T>(u0, u1, u2, u3, cv, ce);
+        return fd_ko_flux<T>(u0, u1, u2, u3, cv, ko[0], ko[1]);
+    } else if constexpr (SCHEME == 2) {
+        return fd_ko3_flux<T>(u0, u1, u2, u3, u4, u5, cv, ko[0], ko[1], ko[2]);
     } else if constexpr (MIX) {
         return tv * weno7_flux<T>(vpos ? u0 : u7, vpos ? u1 : u6, vpos ? u2 : u5, vpos ? u3 : u4, vpos ? u4 : u3,
                                   vpos ? u5 : u2, vpos ? u6 : u1, epsv);
@@ -351,12 +366,13 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     using T = typename std::conditional<FORM == 0, double, float>::type;   // stencil arithmetic
     using TI = typename std::conditional<IN32, float, double>::type;      // stage input as stored
     // Window: R rows around the current one, slot m holding row r + dir (m - CTR).
-    // FD needs rows i-1..i+2 of the face i+1/2.  WENO7 needs rows i-3..i+3 of
+    // FD needs rows i-1..i+2 of the face i+1/2 (i-2..i+3 with KO r = 3,
+    // SCHEME 2).  WENO7 needs rows i-3..i+3 of
     // the upwind-ordered stencil when it marches upwind; with MIX a lane may
     // need the mirrored one, and against the upwind direction (REV) every lane
     // does, rows i-2..i+4, so the window reaches one row further.
-    constexpr int CTR = SCHEME == 0 ? 1 : 3;
-    constexpr int R = SCHEME == 0 ? 4 : (MIX || REV ? 8 : 7);
+    constexpr int CTR = SCHEME == 0 ? 1 : SCHEME == 2 ? 2 : 3;
+    constexpr int R = SCHEME == 0 ? 4 : SCHEME == 2 ? 6 : (MIX || REV ? 8 : 7);
     constexpr int AH = R - 1 - CTR;  // look-ahead distance
     constexpr int NC = 4;                   // components of one species
     constexpr bool AUX0 = STAGE != 0;       // y, or acc in stage 4
@@ -374,7 +390,7 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     const double sgn = sp ? -1.0 : 1.0;
     const T tv = (T)v;
     const T cv = (T)(v * (1.0 / 12.0));
-    const T ce = (T)d.ko16;
+    const T ce[3] = {(T)d.ko[0], (T)d.ko[1], (T)d.ko[2]};
     const T epsv = (T)(v != 0.0 ? d.weno_eps / (v * v) : d.weno_eps);
     const bool vpos = v > 0.0;
 
@@ -689,7 +705,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
     const double ca = sp ? -agl : gl, cb = sp ? agl : gl;
     const double sgn = sp ? -1.0 : 1.0;
     const T cv = (T)(v * (1.0 / 12.0));
-    const T ce = (T)d.ko16;
+    const T k0 = (T)d.ko[0], k1 = (T)d.ko[1];
     const size_t plane = d.ps;
     const int cofs = sp * NC;
     const gchar *xb = (const gchar *)(PAIR == 0 ? (const void *)d.y : d.yb) + (size_t)cofs * plane * sizeof(TI);
@@ -747,7 +763,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
     T fA[NC], fB[NC];   // fluxes on the faces behind rows a and b
 
     auto flux = [&](auto x) -> T {  // FD + KO interface flux from four window rows in dir order
-        return REV ? fd_ko_flux<T>(x(3), x(2), x(1), x(0), cv, ce) : fd_ko_flux<T>(x(0), x(1), x(2), x(3), cv, ce);
+        return REV ? fd_ko_flux<T>(x(3), x(2), x(1), x(0), cv, k0, k1) : fd_ko_flux<T>(x(0), x(1), x(2), x(3), cv, k0, k1);
     };
     auto hamiltonian = [&](const double S[kMomQ], double &h3, double &hr, double &hi) {
         const double A0 = S[0] - v * S[3];
@@ -942,8 +958,9 @@ __device__ __forceinline__ double *wave_lds(double *pool) {
     return WR ? pool + (threadIdx.x >> 6) * kLdsPerWave : nullptr;
 }
 
-// Register budgets (waves per SIMD): FD 4 (128 VGPRs) with one row group per
-// wave, else 3 (168 VGPRs); WENO7 3, else 2.
+// Register budgets (waves per SIMD): FD with KO r <= 2 4 (128 VGPRs) with one
+// row group per wave, else 3 (168 VGPRs); WENO7 and FD with KO r = 3 (two more
+// window rows) 3, else 2.
 template <int SCHEME, bool WR>
 constexpr int kMinWavesPerSimd = SCHEME == 0 ? (WR ? 4 : 3) : (WR ? 3 : 2);
 
@@ -1051,6 +1068,8 @@ template <bool WR>
 hipError_t launch_stage_w(const InstDesc &d, int stage, dim3 grid, dim3 block, hipStream_t st) {
     if (d.scheme == 0) return d.form == 0 ? launch_stage_t<0, 0, WR>(d, stage, grid, block, st)
                                           : launch_stage_t<0, 1, WR>(d, stage, grid, block, st);
+    if (d.scheme == 2) return d.form == 0 ? launch_stage_t<2, 0, WR>(d, stage, grid, block, st)
+                                          : launch_stage_t<2, 1, WR>(d, stage, grid, block, st);
     return d.form == 0 ? launch_stage_t<1, 0, WR>(d, stage, grid, block, st)
                        : launch_stage_t<1, 1, WR>(d, stage, grid, block, st);
 }
@@ -1059,6 +1078,8 @@ hipError_t launch_batch_w(const InstDesc *dd, const WaveTask *tk, int nwt, int s
                           dim3 block, hipStream_t st) {
     if (scheme == 0) return form == 0 ? launch_batch_t<0, 0, WR>(dd, tk, nwt, stage, grid, block, st)
                                       : launch_batch_t<0, 1, WR>(dd, tk, nwt, stage, grid, block, st);
+    if (scheme == 2) return form == 0 ? launch_batch_t<2, 0, WR>(dd, tk, nwt, stage, grid, block, st)
+                                      : launch_batch_t<2, 1, WR>(dd, tk, nwt, stage, grid, block, st);
     return form == 0 ? launch_batch_t<1, 0, WR>(dd, tk, nwt, stage, grid, block, st)
                      : launch_batch_t<1, 1, WR>(dd, tk, nwt, stage, grid, block, st);
 }
@@ -1101,6 +1122,7 @@ int batch_waves_per_cu_t() {
 template <bool WR>
 int batch_waves_per_cu_w(int scheme, int form) {
     if (scheme == 0) return form == 0 ? batch_waves_per_cu_t<0, 0, WR>() : batch_waves_per_cu_t<0, 1, WR>();
+    if (scheme == 2) return form == 0 ? batch_waves_per_cu_t<2, 0, WR>() : batch_waves_per_cu_t<2, 1, WR>();
     return form == 0 ? batch_waves_per_cu_t<1, 0, WR>() : batch_waves_per_cu_t<1, 1, WR>();
 }
 }  // namespace

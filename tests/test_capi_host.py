@@ -33,6 +33,7 @@ def test_default_params_are_the_fiducial_case():
     assert (p.nz, p.nv, p.scheme, p.precision) == (512, 32, 0, 0)
     assert (p.L, p.cfl, p.mu, p.alpha, p.sigma_nu, p.sigma_nubar) == (400.0, 0.4, 1.0, 0.9, 0.6, 0.5)
     assert (p.ko_eps, p.weno_eps, p.pert_amp, p.pert_width) == (0.1, 1e-6, 1e-6, 50.0)
+    assert (p.ko_order, p.quadrature) == (2, cosenu.QUAD_MIDPOINT)
     assert abs(p.theta - 37.0 * 3.141592653589793 / 180.0) < 1e-15
 
 
@@ -40,6 +41,8 @@ def test_default_params_are_the_fiducial_case():
     ("nz", 4), ("nv", 1), ("nv", 0), ("L", 0.0), ("L", float("nan")), ("cfl", 0.0), ("cfl", 2.5),
     ("sigma_nu", 0.0), ("alpha", -0.1), ("pert_amp", 1.5), ("pert_width", 0.0), ("weno_eps", 0.0),
     ("ko_eps", -1.0), ("scheme", 2), ("precision", 7), ("mu", float("inf")),
+    ("ko_order", 0), ("ko_order", 4), ("quadrature", 3), ("quadrature", -1),
+    ("quadrature", 2),  # Simpson's rule with the default even nv = 32
 ])
 def test_invalid_parameters_rejected_before_device(field, value):
     p = cosenu.default_params()
@@ -47,6 +50,13 @@ def test_invalid_parameters_rejected_before_device(field, value):
     h = ctypes.c_void_p()
     assert cosenu.lib().cosenu_create(ctypes.byref(p), ctypes.byref(h)) == cosenu.EINVAL
     assert not h.value
+
+
+def test_ko_order_3_needs_seven_rows():
+    p = cosenu.default_params()
+    p.ko_order, p.nz = 3, 6
+    h = ctypes.c_void_p()
+    assert cosenu.lib().cosenu_create(ctypes.byref(p), ctypes.byref(h)) == cosenu.EINVAL
 
 
 def test_weno_needs_nine_rows():

@@ -100,7 +100,8 @@ def test_batch_autotune_keeps_states_and_results():
         before = [b.get_state(i) for i in range(len(insts))]
         segs = b.autotune()
         assert all(np.array_equal(b.get_state(i), before[i]) for i in range(len(insts)))
-        assert segs[0] == 0 and all(s > 0 for s in segs[1:]), segs
+        # variants 2k + (nv > 32): FD k = 0 (nv 128, 64), WENO7 k = 1 (nv 32, 256); no KO r = 3
+        assert segs[0] == 0 and all(s > 0 for s in segs[1:4]) and segs[4:] == [0, 0], segs
         b.step(7)
         got = [b.get_state(i) for i in range(len(insts))]
     for w, g in zip(insts, got):
