@@ -738,8 +738,12 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
     SIM_CHECK(s);
     HIPCHK(s, hipStreamSynchronize(s->stream));
     // Stages 1..3 write only scratch (Y2, Y3, Y4, acc and the moments of
-    // those stage values), so timing them leaves the state untouched.  The
-    // tuned length is cached per (scheme, form, nv, nz bucket) and path.
+    // those stage values), so timing them leaves the state untouched.  Both
+    // fused pairs are timed: the second writes the new state into the other
+    // state buffer (scratch until the step is taken) and the moments of that
+    // state over those of the current one, which are rebuilt from the state
+    // afterwards with the producer's own arithmetic.  The tuned length is
+    // cached per (kernel variant, form, nv, nz bucket) and path.
     // segment lengths about sqrt(2) apart: the workgroup count of the fused pairs
     // (one per segment) has to land just under a whole number of resident rounds
     const int cands[] = {4, 6, 8, 11, 16, 22, 32, 45, 64, 90, 128, 181, 256};
@@ -752,9 +756,7 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
     for (int c : cands) {
         if (c > s->d.nz) break;
         set_shape(s->d, c);
-        // single stages 1..3, or the first fused pair (stages 1 and 2), which
-        // both leave y and its moments untouched
-        const int ntime = fused(s) ? 1 : 3;
+        const int ntime = fused(s) ? 2 : 3;
         double total = 0.0;
         bool ok = true;
         for (int rep = 0; rep < 4 && ok; ++rep) {
@@ -781,6 +783,7 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
     (void)hipEventDestroy(b);
     s->d = keep;
     set_shape(s->d, best);
+    if (fused(s)) HIPCHK(s, launch_moments_init(s->d, blocks_for(s->d), s->stream));
     store_tuned_seg(s->d.scheme, s->prm.precision, s->prm.nz, s->prm.nv, fused(s), best);
     if (seg_rows) *seg_rows = best;
     return build_graphs(s);

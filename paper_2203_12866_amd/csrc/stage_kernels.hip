@@ -75,6 +75,15 @@ __device__ __forceinline__ double group_sum(double x, int lr_log2) {
     if (lr_log2 >= 6) x += dpp_f64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
     return x;
 }
+// The same with the group size known at compile time (no branches).
+template <int LOG>
+__device__ __forceinline__ double group_sum_c(double x) {
+    if constexpr (LOG >= 1) x += dpp_f64<0xB1, 0xF>(x);
+    if constexpr (LOG >= 2) x += dpp_f64<0x4E, 0xF>(x);
+    if constexpr (LOG >= 3) x += dpp_f64<0x141, 0xF>(x);
+    if constexpr (LOG >= 4) x += dpp_f64<0x140, 0xF>(x);
+    return x;
+}
 
 // Interface flux at i+1/2 whose difference gives, for cell i, dz times the
 // FD4 central derivative term v (u_{i-2} - 8u_{i-1} + 8u_{i+1} - u_{i+2}) / 12
@@ -343,6 +352,15 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
 
 __device__ __forceinline__ void sum_row_parts(const double pv[2], int plog, double S[kMomQ]) {
     const double t0 = group_sum(pv[0], plog), t1 = group_sum(pv[1], plog);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        S[g] = readlane_f64(t0, kPartLanes * g);
+        S[g + 3] = readlane_f64(t1, kPartLanes * g);
+    }
+}
+template <int PLOG>
+__device__ __forceinline__ void sum_row_parts_c(const double pv[2], double S[kMomQ]) {
+    const double t0 = group_sum_c<PLOG>(pv[0]), t1 = group_sum_c<PLOG>(pv[1]);
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         S[g] = readlane_f64(t0, kPartLanes * g);
@@ -670,8 +688,8 @@ __device__ __forceinline__ void moments_group(const InstDesc &d, int task, int l
 // and stage B produces row b = a - 2 dir of the pair's output from the last
 // four Z rows, kept in registers.  Stage B needs the angular moments of Z row
 // b over every chunk and species: each wave stores its six totals of row a in
-// a ring of LDS slots, one barrier per step makes them visible, and two steps
-// later every wave reads the slot lane-distributed and sums it exactly as the
+// a ring of LDS slots, a barrier after every second step makes them visible,
+// and two steps later every wave reads the slot lane-distributed and sums it exactly as the
 // unfused stage reads the moment partials from memory.  So every value, and
 // every moment partial written, is bitwise the one the four single stages
 // produce.  Z covers the segment and two rows on either side (its halo for
@@ -681,9 +699,14 @@ __device__ __forceinline__ void moments_group(const InstDesc &d, int task, int l
 // Bytes per cell and step (8 components): FP64 form 192 + 256 = 448, FP32
 // form 160 + 224 = 384, against 768 and 704 for four single stages.
 // ---------------------------------------------------------------------------
-constexpr int kXchSlots = 4;  // LDS ring of Z moment totals: [slot][part][6]
+// LDS ring of Z moment totals: [slot][part][6].  The barrier sits between the
+// slot writes and reads of every odd step.  A slot written at step s is read
+// at step s + 2, after the barrier of step s or s + 1; it is rewritten at
+// step s + 8, after the barrier of an odd step in s + 3 .. s + 7, which
+// every wave reaches only once its read at step s + 2 is done.
+constexpr int kXchSlots = 8;
 
-template <int FORM, int PAIR, bool REV>
+template <int FORM, int PAIR, bool REV, int PLOG>
 __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int segi, int l, int dir, double *lds,
                                           double *xch) {
     constexpr bool XIN32 = FORM == 1 && PAIR == 1;  // X = Y3, stored in FP32 by the FP32 form
@@ -722,10 +745,18 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
     gdouble *m_out = (gdouble *)(PAIR == 0 ? d.mom[2] : d.mom[0]);
     const int nparts = 2 * vchunks;
     const int part = vc * 2 + sp;
-    const int plog = 32 - __builtin_clz(nparts - 1);
     const int pg = min(l / kPartLanes, 2), pp = min(l % kPartLanes, nparts - 1);
     const bool p_on = l < 3 * kPartLanes && l % kPartLanes < nparts;
     const int poff = pp * kMomQ + pg;
+    // the part sums with a compile-time number of DPP steps, except in the
+    // FP64 form's second pair, whose register budget the freer schedule
+    // overruns (same arithmetic either way)
+    constexpr bool CPLOG = !(FORM == 0 && PAIR == 1);
+    const int plog = 32 - __builtin_clz(nparts - 1);
+    auto part_sums = [&](const double(&pz)[2], double(&S)[kMomQ]) {
+        if constexpr (CPLOG) sum_row_parts_c<PLOG>(pz, S);
+        else sum_row_parts(pz, plog, S);
+    };
 
     const double dzs = dir > 0 ? d.dz_inv : -d.dz_inv;
     const double dt = d.dt, hdt = 0.5 * d.dt, dt6 = d.dt * (1.0 / 6.0);
@@ -788,7 +819,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
             for (int c = 0; c < NC; ++c) dst[c] = ld<double>(accb + (size_t)c * p64, offb);
         }
     };
-    auto compute = [&](int s, const Buf &b) {
+    auto compute = [&](int s, const Buf &b, bool sync) {
         const int a = row_a(s);
         double abl[NC];
         if (!ACC_AHEAD && s >= 4) load_acc(s, abl);
@@ -805,7 +836,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
         double S[kMomQ];
         {
             const double pz[2] = {p_on ? b.pv[0] : 0.0, p_on ? b.pv[1] : 0.0};
-            sum_row_parts(pz, plog, S);
+            part_sums(pz, S);
         }
         double h3, hr, hi, u[NC], kk[NC];
         hamiltonian(S, h3, hr, hi);
@@ -850,7 +881,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
             const double t = wave_row_totals(mt, lds, l);
             if ((l & 7) == 0 && (l >> 3) < kMomQ) xch[((s % kXchSlots) * nparts + part) * kMomQ + (l >> 3)] = t;
         }
-        __syncthreads();
+        if (sync) __syncthreads();
         if (s == 3) {  // flux on the face behind the first stage B row, from Z rows start - 2 dir .. start + dir
 #pragma unroll
             for (int c = 0; c < NC; ++c) fB[c] = flux([&](int m) -> T { return (T)zw[c][m]; });
@@ -866,7 +897,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
         {
             const double *xs = xch + ((s - 2) % kXchSlots) * nparts * kMomQ;
             const double pz[2] = {p_on ? xs[poff] : 0.0, p_on ? xs[poff + 3] : 0.0};
-            sum_row_parts(pz, plog, SB);
+            part_sums(pz, SB);
         }
         // Z window of row b: rows b - dir .. b + 2 dir = zw[0..3]
         double advB[NC];
@@ -931,10 +962,10 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
     }
     for (int s = 0; s < nsteps; s += 2) {
         if (s + 1 < nsteps) issue(s + 1, bufB);
-        compute(s, bufA);
+        compute(s, bufA, false);
         if (s + 1 >= nsteps) break;
         if (s + 2 < nsteps) issue(s + 2, bufA);
-        compute(s + 1, bufB);
+        compute(s + 1, bufB, true);
     }
 }
 
@@ -1011,9 +1042,10 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock, (kMinWavesPerSimd<SCHEME, WR
     }
 }
 
-// Fused stage pairs: one workgroup per segment, one wave per (chunk, species).
-template <int FORM, int PAIR, int NW>
-__global__ __launch_bounds__(kWave *NW, 3) void pair_kernel(InstDesc d) {
+// Fused stage pairs: one workgroup per segment, one wave per (chunk, species);
+// 2^PLOG >= 2 vchunks moment parts per row, so at most 2^PLOG waves.
+template <int FORM, int PAIR, int PLOG>
+__global__ __launch_bounds__(kWave * (1 << PLOG), 3) void pair_kernel(InstDesc d) {
     extern __shared__ __align__(16) double pair_pool[];
     const int nw = blockDim.x >> 6;  // 2 vchunks
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1022,8 +1054,8 @@ __global__ __launch_bounds__(kWave *NW, 3) void pair_kernel(InstDesc d) {
     double *lds = pair_pool + w * kLdsPerWave;
     double *xch = pair_pool + nw * kLdsPerWave;
     const int vc = w >> 1, sp = w & 1;
-    if (kAltDir && (segi & 1)) pair_body<FORM, PAIR, true>(d, vc, sp, segi, lane, -1, lds, xch);
-    else pair_body<FORM, PAIR, false>(d, vc, sp, segi, lane, 1, lds, xch);
+    if (kAltDir && (segi & 1)) pair_body<FORM, PAIR, true, PLOG>(d, vc, sp, segi, lane, -1, lds, xch);
+    else pair_body<FORM, PAIR, false, PLOG>(d, vc, sp, segi, lane, 1, lds, xch);
 }
 
 }  // namespace
@@ -1136,9 +1168,10 @@ bool pair_supported(const InstDesc &d) { return d.scheme == 0 && d.lr_log2 == 6 
 namespace {
 template <int FORM, int PAIR>
 hipError_t launch_pair_t(const InstDesc &d, dim3 grid, dim3 block, size_t shm, hipStream_t st) {
-    const int W = (int)block.x / kWave;
-    if (W <= 4) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 4>), grid, block, shm, st, d);
-    else hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 8>), grid, block, shm, st, d);
+    const int W = (int)block.x / kWave;  // moment parts per row, 2 vchunks
+    if (W <= 2) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 1>), grid, block, shm, st, d);
+    else if (W <= 4) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 2>), grid, block, shm, st, d);
+    else hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 3>), grid, block, shm, st, d);
     return hipGetLastError();
 }
 }  // namespace

@@ -89,3 +89,28 @@ def test_switching_fusion_mid_run_and_checkpoint():
         s.set_state(mid)
         s.step(5)
         assert np.array_equal(s.get_state(), ref)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("precision", [wl.FP64, wl.FP32_ACC64])
+def test_autotune_mid_run_keeps_state_and_results(fused, precision):
+    """The tuner times both fused pairs (or stages 1-3) on the live buffers;
+    the state, its moments and every later step stay bitwise unchanged."""
+    nz, nv = 700, 128
+    w = dict(wl.small_fd(8), nz=nz, nv=nv, L=500.0, omega=0.05, lam=0.2, precision=precision)
+    y0 = wl.random_unit_state(nz, nv, seed=21)
+    ref, mref, cref, _ = _run(w, y0, 10, fused)
+    with cosenu.Sim(w) as s:
+        s.set_fusion(fused)
+        s.set_state(y0)
+        s.step(5)
+        before = s.get_state()
+        m_before = s.moments()
+        seg = s.autotune()
+        assert seg >= 4 and s.info()["seg_rows"] == seg
+        assert np.array_equal(s.get_state(), before)
+        assert np.array_equal(s.moments(), m_before)
+        s.step(5)
+        assert np.array_equal(s.get_state(), ref)
+        assert np.array_equal(s.moments(), mref)
+        assert s.conserved() == cref

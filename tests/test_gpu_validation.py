@@ -11,6 +11,10 @@ the equations decouple into advection (Sec. 4.1) and vacuum oscillation
   with Kreiss-Oliger), as Sec. 4.1 states.
 * Vacuum oscillation of a Gaussian packet (eq:vac_sols) and the minimum of the
   survival probability printed in Sec. 4.2.
+* The effect of Kreiss-Oliger dissipation on a box profile (Appendix B):
+  without it the Fourier amplitudes stay those of the exact solution while
+  the phases are kept only at long wavelengths, which leaves dispersive
+  ripples; with eps = 0.1 the short-wavelength amplitudes are suppressed.
 """
 import math
 
@@ -40,18 +44,18 @@ def _run(nz, nv, L, cfl, scheme, y0, steps, precision=wl.FP64, **kw):
         return s.get_state(), s.info()["dt"]
 
 
-@pytest.mark.parametrize("ko_eps", [0.0, 0.1])
-def test_fd_ko_kernels_match_fourier_propagator(ko_eps):
+@pytest.mark.parametrize("ko_eps,r", [(0.0, 2), (0.1, 2), (0.3, 1), (0.2, 3)])
+def test_fd_ko_kernels_match_fourier_propagator(ko_eps, r):
     nz, nv, L = 48, 4, 30.0
     dz = L / nz
     steps = 25
     y0 = np.random.default_rng(3).uniform(-1, 1, size=(8, nz, nv))
-    y, dt = _run(nz, nv, L, 0.2775, wl.FD_KO, y0, steps, ko_eps=ko_eps)
+    y, dt = _run(nz, nv, L, 0.2775, wl.FD_KO, y0, steps, ko_eps=ko_eps, ko_order=r)
     v = o.velocities(nv)
     for c in range(8):
         for j in range(nv):
             sym = lambda th: (-1j * v[j] * (8 * np.sin(th) - np.sin(2 * th)) / (6 * dz)
-                              - (ko_eps / dz) * np.sin(th / 2) ** 4)
+                              - (ko_eps / dz) * np.sin(th / 2) ** (2 * r))
             expect = spectral_evolve(y0[c, :, j], sym, dt, steps)
             np.testing.assert_allclose(y[c, :, j], expect, rtol=0, atol=1e-12)
 
@@ -139,3 +143,40 @@ def test_kernels_vacuum_oscillation_match_eq_vac_sols(scheme, precision):
     surv = y[0, :, 1].sum() / y0[0, :, 1].sum()
     assert abs(surv - (1 - s2 ** 2 * sn2)) < tol
     assert abs(surv - g["min_survival"]) < 0.5 * 10 ** (-g["min_survival_digits"])
+
+
+@pytest.mark.parametrize("precision", [wl.FP64, wl.FP32_ACC64])
+def test_kreiss_oliger_effect_on_box_profile(precision):
+    nz, nv, L = 400, 2, 400.0                   # dz = 1, v = -0.5, +0.5
+    z = o.positions(nz, L)
+    box = (np.abs(z) < 40.0).astype(float)
+    y0 = np.zeros((8, nz, nv))
+    y0[:, :, 1] = box
+    res = {}
+    for eps in (0.0, 0.1):
+        y, dt = _run(nz, nv, L, 0.4, wl.FD_KO, y0, 250, precision=precision, ko_eps=eps)
+        res[eps] = y[0, :, 1]
+    t = 250 * dt
+    shift = int(round(0.5 * t / (L / nz)))
+    assert abs(0.5 * t - shift) < 1e-9             # the exact solution is the box moved by 100 cells
+    exact = np.roll(box, shift)
+    th = 2 * np.pi * np.fft.fftfreq(nz)
+    fe = np.fft.fft(exact)
+    on = np.abs(fe) > 1e-3 * np.abs(fe).max()      # modes the box actually holds
+    ratio = {e: np.abs(np.fft.fft(u)) / np.maximum(np.abs(fe), 1e-300) for e, u in res.items()}
+    phase = {e: np.angle(np.fft.fft(u) / np.where(on, fe, 1.0)) for e, u in res.items()}
+    hi, lo = on & (np.abs(th) > 2.0), on & (np.abs(th) < 0.3)
+    # no dissipation: every amplitude kept (RK4 alone damps by < 10 % here) ...
+    assert ratio[0.0][on].min() > 0.9 and ratio[0.0][on].max() < 1.0 + 1e-4
+    # ... phases kept at long wavelengths only
+    assert np.abs(phase[0.0][lo]).max() < 0.05
+    assert np.abs(phase[0.0][hi]).max() > 1.0
+    # eps = 0.1: short wavelengths damped by exp(-eps t sin^4(th/2) / dz), far below 1e-3
+    assert ratio[0.1][hi].max() < 1e-3
+    assert np.abs(phase[0.1][lo]).max() < 0.05
+    # the dispersive ripples of the undamped run overshoot the box more
+    over = {e: u.max() - 1.0 for e, u in res.items()}
+    print(f"overshoot without KO {over[0.0]:.3f}, with KO {over[0.1]:.3f}")
+    assert over[0.0] > 0.1 and over[0.1] < over[0.0]
+    # and the undamped run is much further from the exact box
+    assert np.abs(res[0.0] - exact).sum() > 2 * np.abs(res[0.1] - exact).sum()
