@@ -147,6 +147,11 @@ def cpu_baseline(cosenu, w, budget_s):
     return cb, errs
 
 
+# kernel variants of a batch, in the order cosenu_batch_autotune reports them
+BATCH_VARIANTS = ["fd_nv<=32", "fd_nv>32", "weno7_nv<=32", "weno7_nv>32", "fd_ko3_nv<=32", "fd_ko3_nv>32",
+                  "fd_pairs_w2", "fd_pairs_w4", "fd_pairs_w6", "fd_pairs_w8"]
+
+
 def run_batch(cosenu, torch, insts, steps, warmup):
     """The batched workload: every instance advanced by one step graph per
     step, segment lengths chosen in place by the batch autotuner (one per
@@ -168,7 +173,8 @@ def run_batch(cosenu, torch, insts, steps, warmup):
     cells = sum(w["nz"] * w["nv"] for w in insts)
     bytes_step = sum(inf["bytes_per_step"] for inf in infos)
     launch_s = ev_ms / (4.0 * steps) / 1e3
-    return dict(wall=wall, ev_ms=ev_ms, cells=cells, updates=cells * 4.0 * steps / wall,
+    fused = sum(1 for inf in infos if inf["launches_per_step"] == 2)
+    return dict(wall=wall, ev_ms=ev_ms, cells=cells, updates=cells * 4.0 * steps / wall, fused=fused,
                 gbps_model=bytes_step * steps / wall / 1e9, bytes_step=bytes_step,
                 achieved_gbps=bytes_step / 4.0 / launch_s / 1e9, launch_s=launch_s,
                 segs=segs, tune_s=tune_s, nonfinite=bad)
@@ -189,12 +195,14 @@ def batch_main(args, cosenu, torch):
         "config": {"workload": "batch_64", "instances": len(insts), "fd_ko": n_fd, "fv_weno7": len(insts) - n_fd,
                    "cells": r["cells"], "nz_range": [min(w["nz"] for w in insts), max(w["nz"] for w in insts)],
                    "nv_set": sorted({w["nv"] for w in insts}), "form": "FP32 stencils, FP64 moments/commutator/RK4",
-                   "seg_rows_per_variant": dict(zip(["fd_nv<=32", "fd_nv>32", "weno7_nv<=32", "weno7_nv>32"], r["segs"]))},
+                   "seg_rows_per_variant": {k: v for k, v in zip(BATCH_VARIANTS, r["segs"]) if v},
+                   "fused_pair_instances": r["fused"]},
         "hbm_gbps": r["gbps_model"],
         "bytes_per_update": r["bytes_step"] / (r["cells"] * 4.0),
         "roofline": {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": r["achieved_gbps"] / PEAK_HBM_GBPS, "traffic": None,
-                     "kernel": "batch_stage_kernel (FD and WENO7 launches per stage, parallel graph branches)",
+                     "kernel": "batch_pair_kernel (FD fused pairs) and batch_stage_kernel (WENO7, FD nv<=32), "
+                               "one launch chain per variant, concurrent graph branches",
                      "avg_launch_us": r["launch_s"] * 1e6},
         "nonfinite_instances": r["nonfinite"],
     }

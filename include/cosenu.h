@@ -236,10 +236,12 @@ const char *cosenu_last_error(const cosenu_sim *s);
 
 /* ---- batched execution ----------------------------------------------------
  * n independent simulations of any sizes and schemes (one precision for the
- * whole batch, taken from p[0]) advanced together: every RK4 stage of every
- * instance is one persistent kernel launch walking a work list, and a step
- * of the whole batch is one HIP graph.  Instance i behaves exactly like a
- * cosenu_sim created from p[i] with the same launch shape.                  */
+ * whole batch, taken from p[0]) advanced together: per RK4 step, each kernel
+ * variant present runs persistent launches walking a work list (four single
+ * stages, or two fused stage pairs for FD + KO with ko_order <= 2 and
+ * 32 < nv <= 256, as cosenu_sim runs them), and steps of the whole batch are
+ * HIP graphs.  Instance i behaves exactly like a cosenu_sim created from p[i]
+ * (bit for bit, whatever the launch shapes).                                */
 int cosenu_batch_create(const cosenu_params *p, int32_t n, cosenu_batch **out);
 void cosenu_batch_destroy(cosenu_batch *b);
 int cosenu_batch_step(cosenu_batch *b, int64_t nsteps);
@@ -250,13 +252,15 @@ int cosenu_batch_conserved(cosenu_batch *b, int32_t i, cosenu_conserved_t *out);
 int cosenu_batch_info(cosenu_batch *b, int32_t i, cosenu_info_t *out);
 int cosenu_batch_time_steps(cosenu_batch *b, int64_t nsteps, double *ms);
 /* Batch autotuner: chooses the segment length of every kernel variant of the
- * batch (variant 2*k + (nv > 32), k = 0 FD with ko_order <= 2, 1 WENO7, 2 FD
- * with ko_order 3) by timing stages 1-3 of that variant
- * alone for seg in {4, 6, 8, 11, ..., 128} (about sqrt(2) apart); every instance of a variant takes the same
- * length (at most its nz).  Then rebuilds the task lists and re-captures the
- * step graphs.  States, clocks and results are unchanged (results do not
- * depend on the segment length).  seg_rows, if not NULL, receives 6 values
- * (0 for variants absent from the batch).  Synchronises the handle's stream. */
+ * batch by timing that variant alone (single stages 1-3, or both fused pairs)
+ * for seg in {4, 6, 8, 11, ..., 128} (about sqrt(2) apart); every instance of
+ * a variant takes the same length (at most its nz).  Variants: 2*k + (nv > 32)
+ * for single stages, k = 0 FD with ko_order <= 2, 1 WENO7, 2 FD with ko_order
+ * 3; 6 + vchunks - 1 for fused pairs (vchunks = ceil(nv / 64) = 1 .. 4).
+ * Then rebuilds the task lists and re-captures the step graphs.  States,
+ * clocks and results are unchanged (results do not depend on the segment
+ * length).  seg_rows, if not NULL, receives 10 values (0 for variants absent
+ * from the batch).  Synchronises the handle's stream.                       */
 int cosenu_batch_autotune(cosenu_batch *b, int32_t *seg_rows);
 const char *cosenu_batch_last_error(const cosenu_batch *b);
 

@@ -358,8 +358,9 @@ class Batch:
         return ms.value
 
     def autotune(self) -> list:
-        """Segment length per kernel variant 2*k + (nv > 32), k = 0 FD (KO r <= 2),
-        1 WENO7, 2 FD (KO r = 3); 0 where absent."""
-        segs = (ctypes.c_int32 * 6)()
+        """Segment length per kernel variant: 2*k + (nv > 32) for single stages,
+        k = 0 FD (KO r <= 2), 1 WENO7, 2 FD (KO r = 3); 6 + vchunks - 1 for
+        fused stage pairs; 0 where absent."""
+        segs = (ctypes.c_int32 * 10)()
         self._check(_lib().cosenu_batch_autotune(self._h, segs), "cosenu_batch_autotune")
         return list(segs)

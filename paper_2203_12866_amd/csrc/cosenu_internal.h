@@ -71,6 +71,11 @@ int batch_waves_per_cu(int scheme, int form, bool wave_rows);
 // one workgroup of 2 vchunks waves per segment (d.nseg workgroups)
 bool pair_supported(const InstDesc &d);
 hipError_t launch_pair(const InstDesc &d, int pair, hipStream_t st);
+// batched fused stage pairs: W = 2 vchunks waves per workgroup, one (instance,
+// segment) task per workgroup and turn (WaveTask.task0 = segment)
+hipError_t launch_batch_pair(const InstDesc *d_descs, const WaveTask *d_tasks, int ntasks, int form, int pair, int W,
+                             int blocks, hipStream_t st);
+int batch_pair_blocks_per_cu(int form, int W);
 // ---- diagnostics (diag_kernels.hip) ----------------------------------------
 // per (segment, chunk) partials [nrowtasks][kDiagQ]:
 //   0..3 M0 (trace, x, y, z) summed g P - alpha gbar Pbar~ (without dz dv)

@@ -1058,6 +1058,30 @@ __global__ __launch_bounds__(kWave * (1 << PLOG), 3) void pair_kernel(InstDesc d
     else pair_body<FORM, PAIR, false, PLOG>(d, vc, sp, segi, lane, 1, lds, xch);
 }
 
+// Batched fused stage pairs: a persistent grid of workgroups of 2 vchunks
+// waves walks a list of (instance, segment) tasks, sorted by decreasing cost
+// on the host, of instances that all have that many waves per segment.
+template <int FORM, int PAIR, int PLOG>
+__global__ __launch_bounds__(kWave * (1 << PLOG), 3) void batch_pair_kernel(const InstDesc *__restrict__ descs,
+                                                                             const WaveTask *__restrict__ tasks,
+                                                                             int ntasks) {
+    extern __shared__ __align__(16) double pair_pool[];
+    const int nw = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & (kWave - 1);
+    double *lds = pair_pool + w * kLdsPerWave;
+    double *xch = pair_pool + nw * kLdsPerWave;
+    const int vc = w >> 1, sp = w & 1;
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const WaveTask tk = tasks[t];
+        const InstDesc &d = descs[tk.inst];
+        const int segi = tk.task0;
+        if (kAltDir && (segi & 1)) pair_body<FORM, PAIR, true, PLOG>(d, vc, sp, segi, lane, -1, lds, xch);
+        else pair_body<FORM, PAIR, false, PLOG>(d, vc, sp, segi, lane, 1, lds, xch);
+        __syncthreads();  // the next task rewrites the LDS ring from its first slot
+    }
+}
+
 }  // namespace
 
 int groups_per_wave(const InstDesc &d) { return kWave >> d.lr_log2; }
@@ -1176,13 +1200,50 @@ hipError_t launch_pair_t(const InstDesc &d, dim3 grid, dim3 block, size_t shm, h
 }
 }  // namespace
 
+size_t pair_shm_bytes(int W) { return (size_t)(W * kLdsPerWave + kXchSlots * W * kMomQ) * sizeof(double); }
+
 hipError_t launch_pair(const InstDesc &d, int pair, hipStream_t st) {
     if (!pair_supported(d)) return hipErrorInvalidValue;
     const int W = 2 * d.vchunks;
-    const size_t shm = (size_t)(W * kLdsPerWave + kXchSlots * W * kMomQ) * sizeof(double);
+    const size_t shm = pair_shm_bytes(W);
     const dim3 grid(d.nseg), block(kWave * W);
     if (d.form == 0) return pair == 0 ? launch_pair_t<0, 0>(d, grid, block, shm, st) : launch_pair_t<0, 1>(d, grid, block, shm, st);
     return pair == 0 ? launch_pair_t<1, 0>(d, grid, block, shm, st) : launch_pair_t<1, 1>(d, grid, block, shm, st);
+}
+
+namespace {
+template <int FORM, int PAIR, int PLOG>
+const void *batch_pair_fn() {
+    return reinterpret_cast<const void *>(batch_pair_kernel<FORM, PAIR, PLOG>);
+}
+template <int PLOG>
+const void *batch_pair_fn_p(int form, int pair) {
+    if (form == 0) return pair == 0 ? batch_pair_fn<0, 0, PLOG>() : batch_pair_fn<0, 1, PLOG>();
+    return pair == 0 ? batch_pair_fn<1, 0, PLOG>() : batch_pair_fn<1, 1, PLOG>();
+}
+const void *batch_pair_fn_any(int form, int pair, int W) {
+    return W <= 2 ? batch_pair_fn_p<1>(form, pair) : W <= 4 ? batch_pair_fn_p<2>(form, pair) : batch_pair_fn_p<3>(form, pair);
+}
+}  // namespace
+
+hipError_t launch_batch_pair(const InstDesc *d_descs, const WaveTask *d_tasks, int ntasks, int form, int pair, int W,
+                             int blocks, hipStream_t st) {
+    if (W < 2 || W > 8 || (W & 1)) return hipErrorInvalidValue;
+    const void *fn = batch_pair_fn_any(form, pair, W);
+    void *args[] = {(void *)&d_descs, (void *)&d_tasks, (void *)&ntasks};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(kWave * W), args, pair_shm_bytes(W), st);
+}
+
+int batch_pair_blocks_per_cu(int form, int W) {
+    int lo = 1 << 30;
+    for (int pair = 0; pair < 2; ++pair) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_pair_fn_any(form, pair, W), kWave * W,
+                                                         pair_shm_bytes(W)) == hipSuccess &&
+            nb > 0)
+            lo = std::min(lo, nb);
+    }
+    return lo == (1 << 30) ? 1 : lo;
 }
 
 hipError_t launch_batch_stage(const InstDesc *d_descs, const WaveTask *d_tasks, int nwt, int scheme, int form,

@@ -100,8 +100,8 @@ def test_batch_autotune_keeps_states_and_results():
         before = [b.get_state(i) for i in range(len(insts))]
         segs = b.autotune()
         assert all(np.array_equal(b.get_state(i), before[i]) for i in range(len(insts)))
-        # variants 2k + (nv > 32): FD k = 0 (nv 128, 64), WENO7 k = 1 (nv 32, 256); no KO r = 3
-        assert segs[0] == 0 and all(s > 0 for s in segs[1:4]) and segs[4:] == [0, 0], segs
+        # WENO7 single stages (nv 32: variant 2, nv 256: 3); FD fused pairs (nv 64: 6, nv 128: 7)
+        assert [k for k, s in enumerate(segs) if s > 0] == [2, 3, 6, 7], segs
         b.step(7)
         got = [b.get_state(i) for i in range(len(insts))]
     for w, g in zip(insts, got):
@@ -141,3 +141,44 @@ def test_blow_up_is_reported_as_nonfinite():
             s.conserved()
         assert e.value.code == cosenu.ENONFINITE
         assert s.conserved(allow_nonfinite=True)["nonfinite"] > 0
+
+
+@pytest.mark.parametrize("precision", [wl.FP64, wl.FP32_ACC64])
+def test_batch_fused_pairs_parity_and_checkpoint(precision):
+    """FD + KO instances with 32 < nv <= 256 run as fused stage pairs inside
+    the batch (2, 4, 6 and 8 waves per segment), their state alternating
+    between two buffers: odd step counts, reading and restoring a state
+    mid-run, and the result after the restore all match solo runs bit for bit."""
+    shapes = [(wl.FD_KO, 300, 128), (wl.FD_KO, 100, 256), (wl.FD_KO, 97, 130), (wl.FD_KO, 64, 64),
+              (wl.FV_WENO7, 90, 64), (wl.FD_KO, 150, 32)]
+    ws = []
+    for i, (scheme, nz, nv) in enumerate(shapes):
+        w = wl.small_fd(30 + i)
+        w.update(nz=nz, nv=nv, L=0.6 * nz, scheme=scheme, omega=0.04 * i, lam=0.1 * i, precision=precision)
+        ws.append(w)
+    solo3, solo8 = [], []
+    for w in ws:
+        with cosenu.Sim(w) as s:
+            s.step(3)
+            solo3.append(s.get_state())
+            s.step(5)
+            solo8.append(s.get_state())
+    with cosenu.Batch(ws) as b:
+        launches = [b.info(i)["launches_per_step"] for i in range(len(ws))]
+        assert launches == [2, 2, 2, 2, 4, 4], launches
+        b.step(3)
+        mid = [b.get_state(i) for i in range(len(ws))]
+        for i in range(len(ws)):
+            assert np.array_equal(mid[i], solo3[i]), i
+        b.step(5)
+        for i in range(len(ws)):
+            assert np.array_equal(b.get_state(i), solo8[i]), i
+        # restore the step-3 states (the batch now sits at the other parity) and redo
+        for i in range(len(ws)):
+            b.set_state(i, mid[i])
+        b.step(1)
+        b.step(4)
+        for i in range(len(ws)):
+            assert np.array_equal(b.get_state(i), solo8[i]), i
+            c = b.conserved(i)
+            assert c["nonfinite"] == 0
