@@ -182,3 +182,39 @@ def test_batch_fused_pairs_parity_and_checkpoint(precision):
             assert np.array_equal(b.get_state(i), solo8[i]), i
             c = b.conserved(i)
             assert c["nonfinite"] == 0
+
+
+def test_degenerate_calls_are_no_ops_or_rejected():
+    """Zero steps change nothing; empty, oversized or short requests are
+    rejected with EINVAL and leave the handle usable."""
+    import ctypes
+    w = dict(wl.small_fd(3), nz=40, nv=70, L=30.0, omega=0.1)
+    L = cosenu.lib()
+    with cosenu.Sim(w) as s:
+        s.step(2)
+        y = s.get_state()
+        info = s.info()
+        s.step(0)
+        assert s.time_steps(0) >= 0.0
+        assert np.array_equal(s.get_state(), y)
+        assert (s.info()["step"], s.info()["t"]) == (info["step"], info["t"])
+        buf = np.zeros(8 * 41 * 70)
+        p = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        assert L.cosenu_get_rows(s._h, 0, 0, p, buf.size) == cosenu.EINVAL
+        assert L.cosenu_get_rows(s._h, 0, 41, p, buf.size) == cosenu.EINVAL
+        assert L.cosenu_get_rows(s._h, 0, 3, p, 8 * 3 * 70 - 1) == cosenu.EINVAL
+        assert L.cosenu_set_state(s._h, p, 8 * 40 * 70 - 1) == cosenu.EINVAL
+        assert L.cosenu_moments(s._h, p, 40 * 8 - 1) == cosenu.EINVAL
+        assert L.cosenu_step(s._h, -1) == cosenu.EINVAL
+        assert L.cosenu_set_seg_rows(s._h, -1) == cosenu.EINVAL
+        assert L.cosenu_set_fusion(s._h, 2) == cosenu.EINVAL
+        # the handle still works and has not moved
+        assert np.array_equal(s.get_rows(-3, 40), np.roll(y, 3, axis=1))
+        s.step(1)
+        assert s.info()["step"] == info["step"] + 1
+    with cosenu.Batch([w, dict(w, nv=16)]) as b:
+        b.step(0)
+        assert b.info(0)["step"] == 0
+        assert L.cosenu_batch_step(b._h, -1) == cosenu.EINVAL
+        assert L.cosenu_batch_get_state(b._h, 2, p, buf.size) == cosenu.EINVAL
+        assert L.cosenu_batch_get_state(b._h, 0, p, 8 * 40 * 70 - 1) == cosenu.EINVAL
