@@ -9,7 +9,7 @@ ELN-crossing Gaussian family, alpha drawn from the seed), run in the
 FP32-with-FP64-accumulation form (headline) and in the FP64 form.
 
 Output: one JSON line on stdout.  Inputs are resident in HBM before the
-timed region starts.  --gpus N with N > 1 exits: this build runs one GPU.
+timed region starts.  --gpus N with N > 1 exits: the library runs on one GPU.
 """
 import argparse
 import hashlib
@@ -223,7 +223,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU (z-sharded) execution is not built",
+        print("bench.py: the library runs on one GPU only; multi-GPU (z-sharded) execution is not implemented",
               file=sys.stderr)
         sys.exit(2)
 
