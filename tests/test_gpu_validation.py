@@ -11,6 +11,10 @@ the equations decouple into advection (Sec. 4.1) and vacuum oscillation
   with Kreiss-Oliger), as Sec. 4.1 states.
 * Vacuum oscillation of a Gaussian packet (eq:vac_sols) and the minimum of the
   survival probability printed in Sec. 4.2.
+* The fixed-time-step study of Sec. 5 (eq:kappa, Appendix C) on the
+  collective-oscillation setup: with dt fixed and Nz doubling, delta P_max
+  falls at the spatial order for FD + KO (kappa ~ 3) and at about 7 for WENO7
+  until the time-integration error takes over and kappa drops to ~0.
 * The effect of Kreiss-Oliger dissipation on a box profile (Appendix B):
   without it the Fourier amplitudes stay those of the exact solution while
   the phases are kept only at long wavelengths, which leaves dispersive
@@ -180,3 +184,30 @@ def test_kreiss_oliger_effect_on_box_profile(precision):
     assert over[0.0] > 0.1 and over[0.1] < over[0.0]
     # and the undamped run is much further from the exact box
     assert np.abs(res[0.0] - exact).sum() > 2 * np.abs(res[0.1] - exact).sum()
+
+
+def test_fixed_dt_convergence_kappa():
+    """delta P_max after 1000 steps at a fixed dt (C = 1 at Nz = 32768), Nz
+    doubling from 1024; kappa = log2 of successive ratios (eq:kappa)."""
+    nv, L, steps = 100, 1200.0, 1000
+    vmax = 1.0 - 1.0 / nv
+    dt = (L / 32768) / vmax
+    nzs = [1024, 2048, 4096, 8192, 16384, 32768]
+    kappa = {}
+    for scheme in (wl.FD_KO, wl.FV_WENO7):
+        dps = []
+        for nz in nzs:
+            w = dict(wl.small_fd(1), nz=nz, nv=nv, L=L, cfl=dt * vmax / (L / nz), pert_amp=1e-2, phase=0.0,
+                     alpha=0.9, scheme=scheme)
+            with cosenu.Sim(w) as s:
+                assert abs(s.info()["dt"] - dt) < 1e-12 * dt
+                s.step(steps)
+                dps.append(s.conserved()["dP_max"])
+        kappa[scheme] = [math.log2(dps[i] / dps[i + 1]) for i in range(len(dps) - 1)]
+        print(f"scheme {scheme}: dP_max {['%.2e' % x for x in dps]}, kappa {['%.2f' % k for k in kappa[scheme]]}")
+    # FD + KO: spatial error dominates at every Nz, kappa ~ its order 3
+    assert all(2.5 < k < 4.2 for k in kappa[wl.FD_KO]), kappa
+    assert abs(kappa[wl.FD_KO][-1] - 3.0) < 0.3
+    # WENO7: about 7 while the spatial error dominates, then ~0 once the RK4 error at this dt takes over
+    assert kappa[wl.FV_WENO7][0] > 6.0 and kappa[wl.FV_WENO7][1] > 6.0, kappa
+    assert all(abs(k) < 0.5 for k in kappa[wl.FV_WENO7][-2:]), kappa
