@@ -11,6 +11,9 @@ the equations decouple into advection (Sec. 4.1) and vacuum oscillation
   with Kreiss-Oliger), as Sec. 4.1 states.
 * Vacuum oscillation of a Gaussian packet (eq:vac_sols) and the minimum of the
   survival probability printed in Sec. 4.2.
+* The CFL study of Sec. 5 (Fig. collosc_dP_varying_Nz): at fixed Nz, delta P
+  at a fixed time does not depend on C for FD + KO (spatial error dominates)
+  but falls with C for WENO7; doubling Nz improves both.
 * The fixed-time-step study of Sec. 5 (eq:kappa, Appendix C) on the
   collective-oscillation setup: with dt fixed and Nz doubling, delta P_max
   falls at the spatial order for FD + KO (kappa ~ 3) and at about 7 for WENO7
@@ -211,3 +214,25 @@ def test_fixed_dt_convergence_kappa():
     # WENO7: about 7 while the spatial error dominates, then ~0 once the RK4 error at this dt takes over
     assert kappa[wl.FV_WENO7][0] > 6.0 and kappa[wl.FV_WENO7][1] > 6.0, kappa
     assert all(abs(k) < 0.5 for k in kappa[wl.FV_WENO7][-2:]), kappa
+
+
+def test_error_versus_cfl_and_resolution():
+    nv, L, T = 100, 1200.0, 40.0
+    cfls = (0.8, 0.4, 0.2)
+    res = {}
+    for scheme in (wl.FD_KO, wl.FV_WENO7):
+        for nz in (4096, 8192):
+            for cfl in cfls:
+                w = dict(wl.small_fd(1), nz=nz, nv=nv, L=L, cfl=cfl, pert_amp=1e-2, phase=0.0, alpha=0.9,
+                         scheme=scheme)
+                with cosenu.Sim(w) as s:
+                    s.step(int(round(T / s.info()["dt"])))
+                    res[scheme, nz, cfl] = s.conserved()["dP_max"]
+    print({k: "%.2e" % v for k, v in res.items()})
+    for nz in (4096, 8192):
+        fd = [res[wl.FD_KO, nz, c] for c in cfls]
+        assert max(fd) / min(fd) < 1.05, fd                       # FD: C does not matter
+        assert res[wl.FV_WENO7, nz, 0.8] > 5 * res[wl.FV_WENO7, nz, 0.2]  # WENO7: smaller steps help
+    for scheme in (wl.FD_KO, wl.FV_WENO7):
+        for c in cfls:
+            assert res[scheme, 8192, c] < 0.5 * res[scheme, 4096, c]  # doubling Nz helps both
