@@ -9,6 +9,11 @@ the equations decouple into advection (Sec. 4.1) and vacuum oscillation
   (golden fixture) on the upwind side.
 * Measured orders on a smooth profile: 7 (FV WENO7), 4 (central FD), 3 (FD
   with Kreiss-Oliger), as Sec. 4.1 states.
+* Gaussian and boxcar advection at v = 0.5, C = 0.2, t = 600 (Sec. 4.1, eq:box;
+  the paper gives no domain length, L = 1600 here): the box is smeared with a
+  maximum error near 0.5 that does not shrink with Nz while E_2 (eq:E2) does;
+  FD shows Gibbs oscillations and WENO7 none; the spectra match the exact ones
+  at long wavelengths and lose power at short ones, FD more (its KO term).
 * Vacuum oscillation of a Gaussian packet (eq:vac_sols) and the minimum of the
   survival probability printed in Sec. 4.2.
 * The CFL study of Sec. 5 (Fig. collosc_dP_varying_Nz): at fixed Nz, delta P
@@ -236,3 +241,52 @@ def test_error_versus_cfl_and_resolution():
     for scheme in (wl.FD_KO, wl.FV_WENO7):
         for c in cfls:
             assert res[scheme, 8192, c] < 0.5 * res[scheme, 4096, c]  # doubling Nz helps both
+
+
+def _advect_profile(prof, nz, scheme, T=600.0, L=1600.0):
+    """Advect prof in the v = +0.5 bin (nv = 2) to time T; returns (u, exact)."""
+    z = o.positions(nz, L)
+    y0 = np.zeros((8, nz, 2))
+    y0[0, :, 1] = prof(z)
+    with _sim(nz, 2, L, 0.2, scheme) as s:
+        dt = s.info()["dt"]
+        n = int(round(T / dt))
+        assert abs(n * dt - T) < 1e-9 * T
+        s.set_state(y0)
+        s.step(n)
+        u = s.get_state()[0, :, 1]
+    return u, prof((z - 0.5 * T + L / 2) % L - L / 2)
+
+
+def test_gaussian_and_box_advection_statements():
+    box = lambda z: ((z >= -100.0) & (z <= 100.0)).astype(float)
+    gauss = lambda z: np.exp(-z ** 2 / (2 * 10.0 ** 2))
+    E2 = lambda e: float(np.sqrt(np.mean(e ** 2)))
+    res = {}
+    for scheme in (wl.FD_KO, wl.FV_WENO7):
+        for nz in (2000, 4000):
+            res[scheme, nz] = _advect_profile(box, nz, scheme)
+    for scheme in (wl.FD_KO, wl.FV_WENO7):
+        (u2, ex2), (u4, ex4) = res[scheme, 2000], res[scheme, 4000]
+        m2, m4 = np.abs(u2 - ex2).max(), np.abs(u4 - ex4).max()
+        print(f"box scheme {scheme}: max err {m2:.3f} / {m4:.3f}, E2 {E2(u2 - ex2):.3e} / {E2(u4 - ex4):.3e}, "
+              f"overshoot {u2.max() - 1:.2e}")
+        assert 0.3 < m2 < 0.6 and 0.3 < m4 < 0.6 and abs(m4 / m2 - 1) < 0.2   # ~0.5, not shrinking
+        assert E2(u4 - ex4) < 0.85 * E2(u2 - ex2)                             # E_2 shrinks
+        fe, fu = np.abs(np.fft.rfft(ex2)), np.abs(np.fft.rfft(u2))
+        th = 2 * np.pi * np.arange(fe.size) / 2000
+        assert np.abs(fu - fe)[th < 0.2].max() < 1e-2 * fe.max()             # long waves kept
+        assert fu[th > 1.5].max() < 0.1 * fe[th > 1.5].max()                 # short waves lost
+    over_fd = res[wl.FD_KO, 2000][0].max() - 1.0
+    over_fv = res[wl.FV_WENO7, 2000][0].max() - 1.0
+    assert over_fd > 0.05 and abs(over_fv) < 1e-3                           # Gibbs in FD only
+    hi = lambda u: np.abs(np.fft.rfft(u))[int(1.5 * 2000 / (2 * np.pi)) + 1:].max()
+    assert hi(res[wl.FD_KO, 2000][0]) < 1e-2 * hi(res[wl.FV_WENO7, 2000][0])  # FD loses more (KO)
+    # the Gaussian: spectrum nearly identical to the exact one, FD error above FV's
+    errs = {}
+    for scheme in (wl.FD_KO, wl.FV_WENO7):
+        u, ex = _advect_profile(gauss, 2000, scheme)
+        fe, fu = np.abs(np.fft.rfft(ex)), np.abs(np.fft.rfft(u))
+        assert np.abs(fu - fe).max() < 1e-3 * fe.max()
+        errs[scheme] = E2(u - ex)
+    assert errs[wl.FD_KO] > 10 * errs[wl.FV_WENO7]
