@@ -220,6 +220,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fusion", action="store_true", help="four single-stage launches per step")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB between device buffers six times (the reference for the HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -233,6 +235,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(6):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copied {a.numel() * a.element_size()} bytes x 6", file=sys.stderr)
+        return
     if args.workload == "batch_64":
         return batch_main(args, cosenu, torch)
     mk = WORKLOADS[args.workload]
