@@ -150,7 +150,7 @@ def test_batch_fused_pairs_parity_and_checkpoint(precision):
     between two buffers: odd step counts, reading and restoring a state
     mid-run, and the result after the restore all match solo runs bit for bit."""
     shapes = [(wl.FD_KO, 300, 128), (wl.FD_KO, 100, 256), (wl.FD_KO, 97, 130), (wl.FD_KO, 64, 64),
-              (wl.FV_WENO7, 90, 64), (wl.FD_KO, 150, 32)]
+              (wl.FV_WENO7, 90, 64), (wl.FD_KO, 150, 32), (wl.FD_KO, 5, 64), (wl.FD_KO, 6, 200)]
     ws = []
     for i, (scheme, nz, nv) in enumerate(shapes):
         w = wl.small_fd(30 + i)
@@ -165,7 +165,7 @@ def test_batch_fused_pairs_parity_and_checkpoint(precision):
             solo8.append(s.get_state())
     with cosenu.Batch(ws) as b:
         launches = [b.info(i)["launches_per_step"] for i in range(len(ws))]
-        assert launches == [2, 2, 2, 2, 4, 4], launches
+        assert launches == [2, 2, 2, 2, 4, 4, 2, 2], launches
         b.step(3)
         mid = [b.get_state(i) for i in range(len(ws))]
         for i in range(len(ws)):
