@@ -146,7 +146,7 @@ typedef struct {
     int32_t seg_rows;        /* z rows marched by one lane group (launch shape) */
     int32_t lanes_per_row;   /* lanes sharing one z row (power of two <= 64)   */
     int32_t v_chunks;        /* 64-bin chunks per row (1 when nv <= 64)        */
-    int32_t blocks_per_stage;/* workgroups of one stage launch                 */
+    int32_t blocks_per_stage;/* workgroups of one stage (or fused pair) launch */
     double bytes_per_step;   /* algorithmic HBM bytes of one RK4 step          */
     int32_t launches_per_step; /* 4 single stages, or 2 fused stage pairs      */
 } cosenu_info_t;
@@ -164,7 +164,8 @@ int cosenu_params_default(cosenu_params *p);
 int cosenu_create(const cosenu_params *p, cosenu_sim **out);
 void cosenu_destroy(cosenu_sim *s);
 
-/* Enqueues nsteps RK4 steps (4 stage launches each) on the handle's stream;
+/* Enqueues nsteps RK4 steps (4 stage launches each, or 2 fused stage pairs,
+ * see cosenu_set_fusion) on the handle's stream as HIP graph launches;
  * returns without waiting.  nsteps = 0 is a no-op; nsteps < 0 is EINVAL. */
 int cosenu_step(cosenu_sim *s, int64_t nsteps);
 /* Waits for everything enqueued on the handle's stream. */
@@ -186,7 +187,8 @@ int cosenu_get_rows(cosenu_sim *s, int64_t z0, int32_t nrows, double *out, size_
 int cosenu_set_clock(cosenu_sim *s, double t, int64_t step);
 
 /* Angular moments of D = g rho - alpha gbar rhobar^* of the current state,
- * per z row: out[(z*2 + m)*4 + q], m = 0: dv sum_j D_j, m = 1: dv sum_j v_j D_j,
+ * per z row: out[(z*2 + m)*4 + q], m = 0: sum_j w_j D_j, m = 1: sum_j w_j v_j D_j
+ * (w_j the quadrature weights, dv for the midpoint bins),
  * q = 0 D_ee, 1 D_xx, 2 Re D_ex, 3 Im D_ex (eq:ham is H_nunu(v) = mu (m0 - v m1)).
  * n must be >= 8*nz.  FP64. */
 int cosenu_moments(cosenu_sim *s, double *out, size_t n);
@@ -225,10 +227,11 @@ int cosenu_time_steps(cosenu_sim *s, int64_t nsteps, double *ms);
  * zeros.  Synchronises. */
 int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage);
 
-/* Picks seg_rows by timing candidate launch shapes on scratch buffers of
- * the handle's shape (the state is not modified); results are cached per
- * (scheme, precision, nv, nz bucket) and path (fused or not) for the process.  *seg_rows receives
- * the choice (may be NULL). */
+/* Picks seg_rows by timing candidate launch shapes (single stages 1-3, or
+ * both fused pairs) on the handle's buffers; the state, its moments and all
+ * later results are unchanged.  Results are cached per (kernel variant,
+ * precision, nv, nz bucket) and path (fused or not) for the process.
+ * *seg_rows receives the choice (may be NULL).  Synchronises. */
 int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows);
 
 const char *cosenu_strerror(int code);
