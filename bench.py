@@ -57,8 +57,30 @@ def measured_traffic(workload: str, form: str):
     return None if e is None else e.get("bytes_per_launch")
 
 
+def tracked(w, c0, c1):
+    """The quantities the configuration tracks, from the diagnostics at the
+    start and the end of a run: the survival probabilities and the drift of
+    every quantity the discrete scheme conserves at this omega and lambda
+    (N_nu, N_nubar and the trace of M0 always; all of M0 at omega = lambda = 0;
+    M0_z at omega = 0; B.M0 at lambda = 0), relative to N_nu + N_nubar."""
+    scale = abs(c0["N_nu"]) + abs(c0["N_nubar"])
+    d = {"N_nu": c1["N_nu"] - c0["N_nu"], "N_nubar": c1["N_nubar"] - c0["N_nubar"],
+         "M0_trace": c1["M0"][0] - c0["M0"][0]}
+    if w["omega"] == 0.0:
+        d["M0_z"] = c1["M0"][3] - c0["M0"][3]
+    if w["lam"] == 0.0:
+        d["B_dot_M0"] = c1["B_dot_M0"] - c0["B_dot_M0"]
+    if w["omega"] == 0.0 and w["lam"] == 0.0:
+        d["M0_x"] = c1["M0"][1] - c0["M0"][1]
+        d["M0_y"] = c1["M0"][2] - c0["M0"][2]
+    return {"t": c1["t"], "steps": c1["step"], "Pee_nu": c1["Pee_nu"], "Pee_nubar": c1["Pee_nubar"],
+            "dP_max": c1["dP_max"], "max_rel_drift": max(abs(v) for v in d.values()) / scale,
+            "rel_drift": {k: v / scale for k, v in d.items()}}
+
+
 def run_form(cosenu, torch, w, steps, warmup, seg, stage_steps, fused=True):
     sim = cosenu.Sim(w)
+    c0 = sim.conserved()
     sim.bind_torch_stream()
     sim.set_fusion(fused)
     chosen = sim.autotune() if seg is None else seg
@@ -74,6 +96,7 @@ def run_form(cosenu, torch, w, steps, warmup, seg, stage_steps, fused=True):
     stage_ms = sim.time_stages(stage_steps)  # one event pair around every stage launch
     info = sim.info()
     state = sim.get_state()
+    track = tracked(w, c0, sim.conserved())
     sim.close()
     cells = w["nz"] * w["nv"]
     # average launch duration over the timed region: HIP events on the sim's
@@ -81,7 +104,7 @@ def run_form(cosenu, torch, w, steps, warmup, seg, stage_steps, fused=True):
     # pairs per step)
     nl = info["launches_per_step"]
     launch_s = ev_ms / (nl * steps) / 1e3
-    return dict(seg=chosen, wall=wall, ev_ms=ev_ms, stage_ms=stage_ms, info=info, state=state,
+    return dict(seg=chosen, wall=wall, ev_ms=ev_ms, stage_ms=stage_ms, info=info, state=state, tracked=track,
                 updates=cells * 4.0 * steps / wall, launches=nl,
                 gbps_model=info["bytes_per_step"] * steps / wall / 1e9,
                 launch_s=launch_s,
@@ -314,6 +337,9 @@ def main():
         },
         "fp32_speedup_over_fp64": head["updates"] / res["fp64"]["updates"],
         "fp32_vs_fp64_after_run": fp32_vs_fp64,
+        "tracked": {"fp32acc": res["fp32acc"]["tracked"], "fp64": res["fp64"]["tracked"],
+                    "drift_ratio_fp32_over_fp64": res["fp32acc"]["tracked"]["max_rel_drift"] /
+                    max(res["fp64"]["tracked"]["max_rel_drift"], 1e-300)},
     }
     if single is not None:
         out["fp32acc_single_stages"] = {
