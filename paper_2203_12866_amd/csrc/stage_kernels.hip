@@ -12,7 +12,8 @@
 // LR = min(64, pow2ceil(nv)) lanes (nv > 64: several 64-bin chunks, each its own
 // group); a group marches down a segment of `seg` consecutive z rows.  The z
 // stencil is a register window that slides with the march (FD: rows i-1..i+2,
-// WENO7: rows i-3..i+4), so every stage input value is read from memory once
+// or i-2..i+3 with Kreiss-Oliger r = 3; WENO7: rows i-3..i+4), so every stage
+// input value is read from memory once
 // per group plus a halo at the segment ends.  The interface flux F_{i+1/2} is
 // formed once and reused for both neighbouring cells (conservative form for
 // both schemes).
@@ -20,10 +21,15 @@
 // The self-interaction needs two angular moments of every input row
 // (eq:ham: the kernel 1 - v v' is separable, so H_nunu(v) = mu (M0 - v M1)).
 // They are produced by the kernel that writes that row: after the stage
-// combine, each group reduces its 64 bins with an xor butterfly in FP64 and
-// writes one partial per (row, chunk); the consumer adds the chunk partials in
-// chunk order.  The reduction order depends only on nv, so results are
-// bitwise independent of the launch shape.
+// combine, each group reduces its bins in FP64 (through LDS and DPP when a
+// row group fills a wave, by a DPP tree otherwise) and writes one partial per
+// (row, chunk, species); the consumer adds the partials in a fixed order.
+// The reduction order depends only on nv, so results are bitwise independent
+// of the launch shape, of single versus fused stages and of batching.
+//
+// FD + KO with 32 < nv <= 256 also runs as fused stage pairs (pair_body):
+// stages 1 + 2 and 3 + 4 each in one launch, the intermediate stage kept in
+// registers and its moments exchanged between the waves of a workgroup.
 //
 // Runge-Kutta storage (classic RK4, y_new = y + dt/6 (k1 + 2k2 + 2k3 + k4)):
 //   stage 1: in y   -> Y2 = y + dt/2 k1                              (ya)
