@@ -487,7 +487,6 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) {
     if (tuned > 0) set_shape(s->d, tuned);
 
     const int nz = p->nz, nv = p->nv;
-    const size_t cells = (size_t)nz * nv;
     const size_t f64 = 8 * s->d.ps * sizeof(double);
     const size_t ybbytes = 8 * s->d.ps * (p->precision == COSENU_FP64 ? sizeof(double) : sizeof(float));
     void *ptr = nullptr;

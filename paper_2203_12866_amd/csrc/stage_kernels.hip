@@ -243,12 +243,6 @@ __device__ __forceinline__ float fresh_copy(float x) {
     return y;
 }
 
-template <typename T>
-__device__ __forceinline__ T load_as(const void *base, size_t idx, bool f32) {
-    if (f32) return (T)(static_cast<const float *>(base)[idx]);
-    return (T)(static_cast<const double *>(base)[idx]);
-}
-
 // Byte-offset loads and stores from a wave-uniform base: the per-lane offset
 // is 32 bits (planes are limited to 2^29 cells), so the address is formed by
 // the memory unit from a scalar base plus one VGPR.
