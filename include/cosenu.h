@@ -252,6 +252,11 @@ int cosenu_batch_sync(cosenu_batch *b);
 int cosenu_batch_get_state(cosenu_batch *b, int32_t i, double *out, size_t n);
 int cosenu_batch_set_state(cosenu_batch *b, int32_t i, const double *in, size_t n);
 int cosenu_batch_conserved(cosenu_batch *b, int32_t i, cosenu_conserved_t *out);
+/* Instance i's angular moments and z rows, as cosenu_moments and
+ * cosenu_get_rows give them for a single simulation (same layouts, same
+ * checks; EINVAL for i out of range).  Synchronise the handle's stream. */
+int cosenu_batch_moments(cosenu_batch *b, int32_t i, double *out, size_t n);
+int cosenu_batch_get_rows(cosenu_batch *b, int32_t i, int64_t z0, int32_t nrows, double *out, size_t n);
 int cosenu_batch_info(cosenu_batch *b, int32_t i, cosenu_info_t *out);
 int cosenu_batch_time_steps(cosenu_batch *b, int64_t nsteps, double *ms);
 /* Batch autotuner: chooses the segment length of every kernel variant of the

@@ -127,6 +127,8 @@ def _lib():
             "cosenu_batch_get_state": (ctypes.c_int, [vp, i32, dp, sz]),
             "cosenu_batch_set_state": (ctypes.c_int, [vp, i32, dp, sz]),
             "cosenu_batch_conserved": (ctypes.c_int, [vp, i32, ctypes.POINTER(Conserved)]),
+            "cosenu_batch_moments": (ctypes.c_int, [vp, i32, dp, sz]),
+            "cosenu_batch_get_rows": (ctypes.c_int, [vp, i32, ctypes.c_int64, ctypes.c_int32, dp, sz]),
             "cosenu_batch_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(Info)]),
             "cosenu_batch_time_steps": (ctypes.c_int, [vp, i64, dp]),
             "cosenu_batch_autotune": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
@@ -339,6 +341,19 @@ class Batch:
         if a.shape != (8, nz, nv):
             raise ValueError("bad state shape")
         self._check(_lib().cosenu_batch_set_state(self._h, i, _dptr(a), a.size), "cosenu_batch_set_state")
+
+    def moments(self, i: int) -> np.ndarray:
+        """Instance i's per-row angular moments, shape (nz, 2, 4) (as Sim.moments)."""
+        out = np.empty((self.shapes[i][0], 2, 4))
+        self._check(_lib().cosenu_batch_moments(self._h, i, _dptr(out), out.size), "cosenu_batch_moments")
+        return out
+
+    def get_rows(self, i: int, z0: int, nrows: int) -> np.ndarray:
+        """Rows z0 .. z0+nrows-1 (periodic) of instance i, shape (8, nrows, nv)."""
+        out = np.empty((8, int(nrows), self.shapes[i][1]))
+        self._check(_lib().cosenu_batch_get_rows(self._h, i, int(z0), int(nrows), _dptr(out), out.size),
+                    "cosenu_batch_get_rows")
+        return out
 
     def conserved(self, i: int) -> dict:
         c = Conserved()

@@ -122,6 +122,44 @@ std::vector<double> bin_constants(const cosenu_params &p) {
     return c;
 }
 
+// Per-row moments of the state in d.y into out[nz][2][4] (scratch holds the
+// per-chunk partials [nz][vchunks][8]); synchronises st.
+hipError_t moments_to_host(const InstDesc &d, double *scratch, hipStream_t st, double *out) {
+    const int nz = d.nz, vch = d.vchunks;
+    hipError_t e = launch_moments_out(d, scratch, row_blocks_for(d), st);
+    std::vector<double> part((size_t)nz * vch * 8);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(part.data(), scratch, part.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    for (int z = 0; z < nz; ++z) {
+        for (int q = 0; q < 8; ++q) {
+            double acc = 0.0;
+            for (int c = 0; c < vch; ++c) acc += part[((size_t)z * vch + c) * 8 + q];
+            // part holds (D_ee, D_xx, ReD, ImD, v D_ee, ...); out is [z][m][q]
+            out[(size_t)z * 8 + q] = d.dv * acc;
+        }
+    }
+    return hipSuccess;
+}
+
+// nrows z rows of the state in d.y from row z0 (periodic) into out[8][nrows][nv];
+// synchronises st.
+hipError_t rows_to_host(const InstDesc &d, int64_t z0, int nrows, hipStream_t st, double *out) {
+    const int nz = d.nz, nv = d.nv;
+    const int first = (int)(((z0 % nz) + nz) % nz);
+    const int n1 = std::min(nrows, nz - first);  // rows before the periodic seam
+    const size_t rowb = (size_t)nv * sizeof(double);
+    const size_t dpitch = (size_t)nrows * rowb, spitch = d.ps * sizeof(double);
+    hipError_t e = hipMemcpy2DAsync(out, dpitch, d.y + (size_t)first * nv, spitch, (size_t)n1 * rowb, 8,
+                                    hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && n1 < nrows)
+        e = hipMemcpy2DAsync(out + (size_t)n1 * nv, dpitch, d.y, spitch, (size_t)(nrows - n1) * rowb, 8,
+                             hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
+
 double time_step(const cosenu_params &p) {
     // largest |v| over the grid: the outer midpoint, or 1 on a vertex grid
     const double vmax = p.quadrature == COSENU_QUAD_MIDPOINT ? 1.0 - 0.5 * (2.0 / p.nv) : 1.0;
@@ -575,18 +613,8 @@ int cosenu_get_state(cosenu_sim *s, double *out, size_t n) {
 
 int cosenu_get_rows(cosenu_sim *s, int64_t z0, int32_t nrows, double *out, size_t n) {
     SIM_CHECK(s);
-    const int nz = s->d.nz, nv = s->d.nv;
-    if (!out || nrows < 1 || nrows > nz || n < (size_t)8 * nrows * nv) return COSENU_EINVAL;
-    const int first = (int)(((z0 % nz) + nz) % nz);
-    const int n1 = std::min(nrows, nz - first);  // rows before the periodic seam
-    const size_t rowb = (size_t)nv * sizeof(double);
-    const size_t dpitch = (size_t)nrows * rowb, spitch = s->d.ps * sizeof(double);
-    HIPCHK(s, hipMemcpy2DAsync(out, dpitch, s->d.y + (size_t)first * nv, spitch, (size_t)n1 * rowb, 8,
-                               hipMemcpyDeviceToHost, s->stream));
-    if (n1 < nrows)
-        HIPCHK(s, hipMemcpy2DAsync(out + (size_t)n1 * nv, dpitch, s->d.y, spitch, (size_t)(nrows - n1) * rowb, 8,
-                                   hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
+    if (!out || nrows < 1 || nrows > s->d.nz || n < (size_t)8 * nrows * s->d.nv) return COSENU_EINVAL;
+    HIPCHK(s, rows_to_host(s->d, z0, nrows, s->stream, out));
     return COSENU_OK;
 }
 
@@ -607,21 +635,8 @@ int cosenu_set_clock(cosenu_sim *s, double t, int64_t step) {
 
 int cosenu_moments(cosenu_sim *s, double *out, size_t n) {
     SIM_CHECK(s);
-    const int nz = s->d.nz, vch = s->d.vchunks;
-    if (!out || n < (size_t)8 * nz) return COSENU_EINVAL;
-    HIPCHK(s, launch_moments_out(s->d, s->mom_out, row_blocks_for(s->d), s->stream));
-    std::vector<double> part((size_t)nz * vch * 8);
-    HIPCHK(s, hipMemcpyAsync(part.data(), s->mom_out, part.size() * sizeof(double), hipMemcpyDeviceToHost,
-                             s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
-    for (int z = 0; z < nz; ++z) {
-        for (int q = 0; q < 8; ++q) {
-            double acc = 0.0;
-            for (int c = 0; c < vch; ++c) acc += part[((size_t)z * vch + c) * 8 + q];
-            // part holds (D_ee, D_xx, ReD, ImD, v D_ee, ...); out is [z][m][q]
-            out[(size_t)z * 8 + q] = s->d.dv * acc;
-        }
-    }
+    if (!out || n < (size_t)8 * s->d.nz) return COSENU_EINVAL;
+    HIPCHK(s, moments_to_host(s->d, s->mom_out, s->stream, out));
     return COSENU_OK;
 }
 

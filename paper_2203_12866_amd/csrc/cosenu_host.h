@@ -23,6 +23,8 @@ void set_shape(InstDesc &d, int seg);
 double bytes_per_cell_step(int form);
 double bytes_per_cell_step_fused(int form);
 void fill_desc_constants(const cosenu_params &p, InstDesc &d);
+hipError_t moments_to_host(const InstDesc &d, double *scratch, hipStream_t st, double *out);
+hipError_t rows_to_host(const InstDesc &d, int64_t z0, int nrows, hipStream_t st, double *out);
 void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vector<double> &part, double ee0n,
                       double ee0b, double t, int64_t step, cosenu_conserved_t *out);
 // tuned segment length per (kernel variant, form, nv, nz bucket) and path (fused stage pairs or single stages); 0 if none

@@ -182,6 +182,14 @@ def test_batch_fused_pairs_parity_and_checkpoint(precision):
             assert np.array_equal(b.get_state(i), solo8[i]), i
             c = b.conserved(i)
             assert c["nonfinite"] == 0
+        # per-instance moments and row slabs (across the periodic seam) as a solo run gives them
+        for i, w in enumerate(ws):
+            with cosenu.Sim(w) as s:
+                s.set_state(solo8[i])
+                m_solo = s.moments()
+            assert np.array_equal(b.moments(i), m_solo), i
+            nz = w["nz"]
+            assert np.array_equal(b.get_rows(i, nz - 2, min(nz, 4)), np.roll(solo8[i], 2, axis=1)[:, :min(nz, 4)]), i
 
 
 def test_degenerate_calls_are_no_ops_or_rejected():
