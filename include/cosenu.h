@@ -256,6 +256,8 @@ int cosenu_batch_conserved(cosenu_batch *b, int32_t i, cosenu_conserved_t *out);
  * cosenu_get_rows give them for a single simulation (same layouts, same
  * checks; EINVAL for i out of range).  Synchronise the handle's stream. */
 int cosenu_batch_moments(cosenu_batch *b, int32_t i, double *out, size_t n);
+/* Sets instance i's clock (with cosenu_batch_set_state, to resume a checkpoint). */
+int cosenu_batch_set_clock(cosenu_batch *b, int32_t i, double t, int64_t step);
 int cosenu_batch_get_rows(cosenu_batch *b, int32_t i, int64_t z0, int32_t nrows, double *out, size_t n);
 int cosenu_batch_info(cosenu_batch *b, int32_t i, cosenu_info_t *out);
 int cosenu_batch_time_steps(cosenu_batch *b, int64_t nsteps, double *ms);

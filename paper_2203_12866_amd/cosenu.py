@@ -128,6 +128,7 @@ def _lib():
             "cosenu_batch_set_state": (ctypes.c_int, [vp, i32, dp, sz]),
             "cosenu_batch_conserved": (ctypes.c_int, [vp, i32, ctypes.POINTER(Conserved)]),
             "cosenu_batch_moments": (ctypes.c_int, [vp, i32, dp, sz]),
+            "cosenu_batch_set_clock": (ctypes.c_int, [vp, i32, ctypes.c_double, i64]),
             "cosenu_batch_get_rows": (ctypes.c_int, [vp, i32, ctypes.c_int64, ctypes.c_int32, dp, sz]),
             "cosenu_batch_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(Info)]),
             "cosenu_batch_time_steps": (ctypes.c_int, [vp, i64, dp]),
@@ -341,6 +342,9 @@ class Batch:
         if a.shape != (8, nz, nv):
             raise ValueError("bad state shape")
         self._check(_lib().cosenu_batch_set_state(self._h, i, _dptr(a), a.size), "cosenu_batch_set_state")
+
+    def set_clock(self, i: int, t: float, step: int):
+        self._check(_lib().cosenu_batch_set_clock(self._h, int(i), float(t), int(step)), "cosenu_batch_set_clock")
 
     def moments(self, i: int) -> np.ndarray:
         """Instance i's per-row angular moments, shape (nz, 2, 4) (as Sim.moments)."""

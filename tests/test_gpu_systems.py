@@ -176,8 +176,10 @@ def test_batch_fused_pairs_parity_and_checkpoint(precision):
         # restore the step-3 states (the batch now sits at the other parity) and redo
         for i in range(len(ws)):
             b.set_state(i, mid[i])
+            b.set_clock(i, 3 * b.info(i)["dt"], 3)
         b.step(1)
         b.step(4)
+        assert all(b.info(i)["step"] == 8 for i in range(len(ws)))
         for i in range(len(ws)):
             assert np.array_equal(b.get_state(i), solo8[i]), i
             c = b.conserved(i)
