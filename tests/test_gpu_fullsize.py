@@ -4,6 +4,12 @@ configuration bench.py times (autotuned segment length).
 * FD + KO, 16384 x 128: after 150 GPU steps from the initial data, one more
   GPU step is compared with one oracle step from the same (downloaded)
   state, over the whole grid.
+* Over the workloads' full lengths (FD 2000 steps, WENO7 5000 steps, into
+  flavour conversion), the FP32 form against the FP64 form: off-diagonals
+  within 1e-5 relative while the FD run stays linear, angle-averaged survival
+  probabilities within 1e-6 once WENO7 is nonlinear, and the drift of every
+  conserved quantity within 10x the FP64 form's (with a floor of a few
+  hundred FP64 ulps).
 * FV WENO7, 65536 x 256 (omega = 1e-3): one step of the oracle on periodic
   z-slabs cut from the GPU state with a 16-row margin (4 stages x 4 rows of
   WENO7 halo) is compared with the GPU step on the slab interiors, at the
@@ -93,3 +99,39 @@ def test_fv_1048576x512_windows_fp32acc():
         print(f"window at {a}: max abs {err:.3e}")
         assert err <= 1e-7, (a, err)
         assert np.isfinite(got).all()
+
+
+def _full_run(w):
+    with cosenu.Sim(w) as s:
+        s.autotune()
+        c0 = s.conserved()
+        s.step(w["steps"])
+        c1 = s.conserved()
+        y = s.get_state()
+    scale = abs(c0["N_nu"]) + abs(c0["N_nubar"])
+    keys = ["N_nu", "N_nubar"]
+    d = [abs(c1[k] - c0[k]) for k in keys] + [abs(c1["M0"][0] - c0["M0"][0])]
+    if w["omega"] == 0.0:
+        d.append(abs(c1["M0"][3] - c0["M0"][3]))
+    if w["lam"] == 0.0:
+        d.append(abs(c1["B_dot_M0"] - c0["B_dot_M0"]))
+    return y, c1, max(d) / scale
+
+
+@pytest.mark.parametrize("which", ["fd_16384x128", "fv_65536x256"])
+def test_fp32_form_tracks_fp64_over_full_run(which):
+    mk = wl.fd_16384x128 if which == "fd_16384x128" else wl.fv_65536x256
+    y64, c64, d64 = _full_run(mk(precision=wl.FP64))
+    y32, c32, d32 = _full_run(mk(precision=wl.FP32_ACC64))
+    rel_off = float(np.abs(y32[2:4] - y64[2:4]).max() / np.abs(y64[2:4]).max())
+    print(f"{which}: steps {c64['step']}, Pee {c64['Pee_nu']:.10f} / {c32['Pee_nu']:.10f}, "
+          f"offdiag rel {rel_off:.2e}, drift FP64 {d64:.2e} FP32 {d32:.2e}")
+    assert c32["nonfinite"] == 0 and c64["nonfinite"] == 0
+    if which == "fd_16384x128":
+        assert c64["Pee_nu"] > 1 - 1e-9              # still linear
+        assert rel_off <= 1e-5
+    else:
+        assert c64["Pee_nu"] < 0.9                     # flavour conversion has set in
+    assert abs(c32["Pee_nu"] - c64["Pee_nu"]) < 1e-6 and abs(c32["Pee_nubar"] - c64["Pee_nubar"]) < 1e-6
+    assert d64 < 1e-12
+    assert d32 <= max(10 * d64, 500 * 2.2e-16)
