@@ -10,7 +10,11 @@ forms (no self-interaction or homogeneous data):
   pure nu_e packet moving at v = 0.5, and the minimum survival probability
   the paper states for omega = 0.1, theta = 37 degrees (golden fixture);
 * homogeneous data with self-interaction: |P| of every bin is conserved by
-  the exact flow, so the RK4 drift must fall as dt^4.
+  the exact flow, so the RK4 drift must fall as dt^4;
+* a second transcription of eq:ham and eq:eom with complex 2x2 matrices in
+  numpy (H rho - rho H, the integral as a weighted sum over the grid) on
+  random Hermitian states, homogeneous in z so that advection drops out,
+  matches the oracle's real-component right-hand side for every quadrature.
 """
 import math
 
@@ -112,3 +116,49 @@ def test_homogeneous_self_interaction_conserves_polarisation_length_to_fourth_or
         drift.append(d)
     assert drift[0] > 1e-12
     assert abs(math.log2(drift[0] / drift[1]) - 4.0) < 0.3, drift
+
+
+def _hermitian_states(rng, nv):
+    """nv random density matrices rho_j (Hermitian, trace near 1)."""
+    a = rng.uniform(0.2, 0.8, nv)
+    b = rng.normal(scale=0.3, size=nv) + 1j * rng.normal(scale=0.3, size=nv)
+    out = np.zeros((nv, 2, 2), dtype=complex)
+    out[:, 0, 0], out[:, 1, 1], out[:, 0, 1], out[:, 1, 0] = a, 1 - a + rng.uniform(-0.1, 0.1, nv), b, np.conj(b)
+    return out
+
+
+@pytest.mark.parametrize("quad,nv", [(o.QUAD_MIDPOINT, 6), (o.QUAD_TRAPEZOID, 6), (o.QUAD_SIMPSON, 7)])
+@pytest.mark.parametrize("scheme", [o.FD_KO, o.FV_WENO7])
+def test_rhs_equals_complex_matrix_transcription(quad, nv, scheme):
+    rng = np.random.default_rng(41 + nv + 3 * scheme)
+    nz = 9
+    mu, omega, theta, lam, alpha = 1.3, 0.7, 0.61, 0.45, 0.83
+    g, gb = rng.uniform(0.1, 1.0, nv), rng.uniform(0.1, 1.0, nv)
+    rho, rhob = _hermitian_states(rng, nv), _hermitian_states(rng, nv)
+    y = np.zeros((8, nz, nv))
+    for base, m in ((0, rho), (4, rhob)):
+        y[base] = m[:, 0, 0].real
+        y[base + 1] = m[:, 1, 1].real
+        y[base + 2] = m[:, 0, 1].real
+        y[base + 3] = m[:, 0, 1].imag
+    p = o.Problem(nz=nz, nv=nv, L=7.0, dt=0.1, mu=mu, omega=omega, theta=theta, lam=lam, alpha=alpha,
+                  scheme=scheme, ko_eps=0.1, g_nu=g, g_nubar=gb, quad=quad)
+    k = o.rhs(p, y)
+    # eq:ham: H = H_vac + H_m + mu sum_l w_l (1 - v v_l) [g rho - alpha gbar rhobar^*]_l,
+    #         Hbar = H_vac - H_m - mu sum_l w_l (1 - v v_l) [g rho^* - alpha gbar rhobar]_l
+    v = np.linspace(-1, 1, nv) if quad != o.QUAD_MIDPOINT else -1 + (np.arange(nv) + 0.5) * 2 / nv
+    w = o.vweights(nv, quad)
+    hvac = 0.5 * omega * np.array([[-math.cos(2 * theta), math.sin(2 * theta)],
+                                   [math.sin(2 * theta), math.cos(2 * theta)]])
+    hm = np.diag([lam, 0.0])
+    grho, gbrhob = g[:, None, None] * rho, gb[:, None, None] * rhob
+    for j in range(nv):
+        kern = (w * (1 - v[j] * v))[:, None, None]
+        H = hvac + hm + mu * np.sum(kern * (grho - alpha * np.conj(gbrhob)), axis=0)
+        Hb = hvac - hm - mu * np.sum(kern * (np.conj(grho) - alpha * gbrhob), axis=0)
+        for base, m, HH in ((0, rho[j], H), (4, rhob[j], Hb)):
+            c = -1j * (HH @ m - m @ HH)
+            got = (k[base, :, j], k[base + 1, :, j], k[base + 2, :, j], k[base + 3, :, j])
+            want = (c[0, 0].real, c[1, 1].real, c[0, 1].real, c[0, 1].imag)
+            for a, b in zip(got, want):
+                np.testing.assert_allclose(a, b, rtol=0, atol=1e-13)
