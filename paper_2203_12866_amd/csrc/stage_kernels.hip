@@ -706,9 +706,10 @@ __device__ __forceinline__ void moments_group(const InstDesc &d, int task, int l
 // every wave reaches only once its read at step s + 2 is done.
 constexpr int kXchSlots = 8;
 
-// FULL: nv is a multiple of 64 and there are exactly 2^PLOG moment parts, so
-// every lane holds a bin and every lane of a part group a part (no masks).
-template <int FORM, int PAIR, bool REV, int PLOG, bool FULL>
+// FULL (for nv a multiple of 64 with exactly 2^PLOG moment parts): bit 0
+// drops the lane masks (every lane holds a bin), bit 1 the part masks (every
+// lane of a part group holds a part).
+template <int FORM, int PAIR, bool REV, int PLOG, int FULL>
 __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int segi, int l, int dir, double *lds,
                                           double *xch) {
     constexpr bool XIN32 = FORM == 1 && PAIR == 1;  // X = Y3, stored in FP32 by the FP32 form
@@ -717,7 +718,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
     constexpr int NC = 4, R = 4, CTR = 1, AH = 2;
     const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
     const int j = vc * kWave + l;
-    const bool lane_on = FULL || j < nv;
+    const bool lane_on = (FULL & 1) || j < nv;
     const int jl = lane_on ? j : nv - 1;
     const int z0 = segi * d.seg, z1 = min(nz, z0 + d.seg);
     const int nrows = z1 - z0;
@@ -749,7 +750,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
     const int part = vc * 2 + sp;
     const int pg = min(l / kPartLanes, 2), pp = min(l % kPartLanes, nparts - 1);
     // FULL: lanes outside the three read groups sum parts that nobody reads
-    const bool p_on = FULL || (l < 3 * kPartLanes && l % kPartLanes < nparts);
+    const bool p_on = (FULL & 2) || (l < 3 * kPartLanes && l % kPartLanes < nparts);
     const int poff = pp * kMomQ + pg;
     // the part sums with a compile-time number of DPP steps, except in the
     // FP64 form's second pair, whose register budget the freer schedule
@@ -1047,7 +1048,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock, (kMinWavesPerSimd<SCHEME, WR
 
 // Fused stage pairs: one workgroup per segment, one wave per (chunk, species);
 // 2^PLOG >= 2 vchunks moment parts per row, so at most 2^PLOG waves.
-template <int FORM, int PAIR, int PLOG, bool FULL>
+template <int FORM, int PAIR, int PLOG, int FULL>
 __global__ __launch_bounds__(kWave * (1 << PLOG), 3) void pair_kernel(InstDesc d) {
     extern __shared__ __align__(16) double pair_pool[];
     const int nw = blockDim.x >> 6;  // 2 vchunks
@@ -1079,8 +1080,8 @@ __global__ __launch_bounds__(kWave * (1 << PLOG), 3) void batch_pair_kernel(cons
         const WaveTask tk = tasks[t];
         const InstDesc &d = descs[tk.inst];
         const int segi = tk.task0;
-        if (kAltDir && (segi & 1)) pair_body<FORM, PAIR, true, PLOG, false>(d, vc, sp, segi, lane, -1, lds, xch);
-        else pair_body<FORM, PAIR, false, PLOG, false>(d, vc, sp, segi, lane, 1, lds, xch);
+        if (kAltDir && (segi & 1)) pair_body<FORM, PAIR, true, PLOG, 0>(d, vc, sp, segi, lane, -1, lds, xch);
+        else pair_body<FORM, PAIR, false, PLOG, 0>(d, vc, sp, segi, lane, 1, lds, xch);
         __syncthreads();  // the next task rewrites the LDS ring from its first slot
     }
 }
@@ -1196,19 +1197,20 @@ namespace {
 template <int FORM, int PAIR>
 hipError_t launch_pair_t(const InstDesc &d, dim3 grid, dim3 block, size_t shm, hipStream_t st) {
     const int W = (int)block.x / kWave;  // moment parts per row, 2 vchunks
-    // the mask-free copy only for the FP32 form's second pair: in the other
-    // kernels the registers it frees are taken by a freer schedule, which spills
-    constexpr bool kFullCopy = FORM == 1 && PAIR == 1;
-    const bool full = kFullCopy && d.nv % kWave == 0 && (W & (W - 1)) == 0;
+    // mask-free copies in the FP32 form only (both masks in its second pair,
+    // the part masks in its first): elsewhere the registers they free are
+    // taken by a freer schedule, which spills
+    constexpr int kFull = FORM == 1 ? (PAIR == 1 ? 3 : 2) : 0;
+    const bool full = kFull != 0 && d.nv % kWave == 0 && (W & (W - 1)) == 0;
     if (W <= 2) {
-        if (full) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 1, kFullCopy>), grid, block, shm, st, d);
-        else hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 1, false>), grid, block, shm, st, d);
+        if (full) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 1, kFull>), grid, block, shm, st, d);
+        else hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 1, 0>), grid, block, shm, st, d);
     } else if (W <= 4) {
-        if (full) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 2, kFullCopy>), grid, block, shm, st, d);
-        else hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 2, false>), grid, block, shm, st, d);
+        if (full) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 2, kFull>), grid, block, shm, st, d);
+        else hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 2, 0>), grid, block, shm, st, d);
     } else {
-        if (full) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 3, kFullCopy>), grid, block, shm, st, d);
-        else hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 3, false>), grid, block, shm, st, d);
+        if (full) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 3, kFull>), grid, block, shm, st, d);
+        else hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 3, 0>), grid, block, shm, st, d);
     }
     return hipGetLastError();
 }
