@@ -771,15 +771,19 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
         if (c > s->d.nz) break;
         set_shape(s->d, c);
         const int ntime = fused(s) ? 2 : 3;
-        double total = 0.0;
+        // the fastest of five timed repetitions (after one to warm up), each
+        // three passes over the launches: candidates a few percent apart have
+        // to be told apart through run-to-run jitter
+        double total = 1e300;
         bool ok = true;
-        for (int rep = 0; rep < 4 && ok; ++rep) {
+        for (int rep = 0; rep < 6 && ok; ++rep) {
             ok = hipEventRecord(a, s->stream) == hipSuccess;
-            for (int stage = 0; stage < ntime && ok; ++stage) ok = launch_k(s, stage, s->stream) == hipSuccess;
+            for (int pass = 0; pass < 3 && ok; ++pass)
+                for (int stage = 0; stage < ntime && ok; ++stage) ok = launch_k(s, stage, s->stream) == hipSuccess;
             ok = ok && hipEventRecord(b, s->stream) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
             float f = 0.f;
             ok = ok && hipEventElapsedTime(&f, a, b) == hipSuccess;
-            if (rep > 0) total += f;  // first repetition warms up
+            if (rep > 0) total = std::min(total, (double)f);
         }
         if (!ok) {
             (void)hipEventDestroy(a);
