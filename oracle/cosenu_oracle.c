@@ -8,8 +8,9 @@
  * library: every formula below is written out again from the paper.
  *
  * It is written to be checked against the paper by eye, not to be fast:
- *   - the self-interaction integral is the literal Riemann sum of eq:ham for
- *     every (z, v) pair, O(Nv) per cell, for H and for Hbar separately;
+ *   - the self-interaction integral is the literal quadrature sum of eq:ham
+ *     (Riemann, trapezoid or Simpson weights) for every (z, v) pair, O(Nv)
+ *     per cell, for H and for Hbar separately;
  *   - the commutators are 2x2 complex matrix products;
  *   - the Kreiss-Oliger operator is built by composing D+ and D- r times;
  *   - WENO7 follows the steps of Appendix A in order (candidates eq:f4s,
