@@ -58,12 +58,21 @@ using gdouble = __attribute__((address_space(1))) double;
 __device__ __forceinline__ int wrap_row(int r, int nz) { return r < 0 ? r + nz : (r >= nz ? r - nz : r); }
 
 // Cross-lane move of an FP64 value with a fixed DPP pattern (two 32-bit
-// halves); lanes of rows outside ROW_MASK receive 0.
+// halves); lanes of rows outside ROW_MASK receive 0.  With every row enabled
+// no lane keeps its old value, so the move takes none (bound_ctrl set: a
+// source lane out of range would read 0, as with an old value of 0), which
+// spares the compiler an instruction that zeroes the destination first.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_f64(double x) {
     const long long b = __builtin_bit_cast(long long, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROW_MASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+    int lo, hi;
+    if constexpr (ROW_MASK == 0xF) {
+        lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+        hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROW_MASK, 0xF, false);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+    }
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
@@ -253,6 +262,21 @@ __device__ __forceinline__ T ld(const gchar *base, uint32_t off) {
 template <typename T>
 __device__ __forceinline__ void st(gchar *base, uint32_t off, T v) {
     *reinterpret_cast<__attribute__((address_space(1))) T *>(base + off) = v;
+}
+// The same with the non-temporal hint, for the streams that a kernel touches
+// once per cell: every stage output (read only by the next launch) and, in the
+// second fused pair, acc and the y operand of stage 3.  Marked as streaming,
+// they do not displace the window rows that a workgroup and its neighbours
+// re-read from the caches (+7% for four single stages, +10% for the fused
+// pairs on FD + KO 16384 x 128, measured; a non-temporal load of the y operand
+// of a single stage was slower, so those keep the plain load).
+template <typename T>
+__device__ __forceinline__ void st_nt(gchar *base, uint32_t off, T v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<__attribute__((address_space(1))) T *>(base + off));
+}
+template <typename T>
+__device__ __forceinline__ T ld_nt(const gchar *base, uint32_t off) {
+    return __builtin_nontemporal_load(reinterpret_cast<const __attribute__((address_space(1))) T *>(base + off));
 }
 
 // Moment integrands of one species' four components for one bin: the
@@ -556,7 +580,7 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
             } else if constexpr (STAGE == 1) {
                 const double y2 = centre;
                 o[c] = a0[c] + hdt * kk[c];
-                if (on) st<double>(accw + (size_t)c * p64, off64, ((a0[c] + y2) + dt * kk[c]) * third);
+                if (on) st_nt<double>(accw + (size_t)c * p64, off64, ((a0[c] + y2) + dt * kk[c]) * third);
             } else if constexpr (STAGE == 2) {
                 o[c] = a0[c] + dt * kk[c];
             } else {
@@ -564,8 +588,8 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
                 o[c] = (a0[c] + y4 * third) + dt6 * kk[c];
             }
             if (on) {
-                if constexpr (out_es == 8) st<double>(outb + (size_t)c * pout, offo, o[c]);
-                else st<float>(outb + (size_t)c * pout, offo, (float)o[c]);
+                if constexpr (out_es == 8) st_nt<double>(outb + (size_t)c * pout, offo, o[c]);
+                else st_nt<float>(outb + (size_t)c * pout, offo, (float)o[c]);
             }
             if (FORM == 1) o[c] = (double)(float)o[c];  // the next stage sees FP32 values
             if (!on) o[c] = 0.0;
@@ -788,7 +812,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
         if constexpr (PAIR == 1) {
             const uint32_t offa = (uint32_t)(ar * nv + jl) * 8u;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) b.ya[c] = ld<double>(yb8 + (size_t)c * p64, offa);
+            for (int c = 0; c < NC; ++c) b.ya[c] = ld_nt<double>(yb8 + (size_t)c * p64, offa);
         }
     };
 
@@ -820,7 +844,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
             const int br = s >= 4 ? row_a(s) - 2 * dir : start;  // stage B row (in [z0, z1) from s = 4)
             const uint32_t offb = (uint32_t)(br * nv + jl) * 8u;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) dst[c] = ld<double>(accb + (size_t)c * p64, offb);
+            for (int c = 0; c < NC; ++c) dst[c] = ld_nt<double>(accb + (size_t)c * p64, offb);
         }
     };
     auto compute = [&](int s, const Buf &b, bool sync) {
@@ -924,13 +948,13 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
             const double zc = zw[c][1];  // exact Z at row b
             if constexpr (PAIR == 0) {   // stage 2: Y3 and acc
                 o[c] = lag[c] + hdt * kk[c];
-                if (lane_on) st<double>(accw + (size_t)c * p64, off64, ((lag[c] + zc) + dt * kk[c]) * third);
+                if (lane_on) st_nt<double>(accw + (size_t)c * p64, off64, ((lag[c] + zc) + dt * kk[c]) * third);
             } else {                     // stage 4: the new state
                 o[c] = (ab[c] + zc * third) + dt6 * kk[c];
             }
             if (lane_on) {
-                if constexpr (out_es == 8) st<double>(outb + (size_t)c * pout, offo, o[c]);
-                else st<float>(outb + (size_t)c * pout, offo, (float)o[c]);
+                if constexpr (out_es == 8) st_nt<double>(outb + (size_t)c * pout, offo, o[c]);
+                else st_nt<float>(outb + (size_t)c * pout, offo, (float)o[c]);
             }
             if (FORM == 1) o[c] = (double)(float)o[c];
             if (!lane_on) o[c] = 0.0;
