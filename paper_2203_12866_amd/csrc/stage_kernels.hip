@@ -212,46 +212,6 @@ __device__ __forceinline__ void write_row_moments(double m[kMomQ], int lr_log2, 
     }
 }
 
-// Row totals of the six integrands over the 64 lanes of a wave (one row group
-// per wave) through the wave's LDS scratch: every lane stores its six values;
-// lane 8q + p adds the eight values of quantity q held by lanes 8p .. 8p+7;
-// three DPP steps combine the eight partial sums of q (every lane of the
-// eight ends with the same total) and lane 8q writes it.  The association
-// order is fixed.  LDS operations of one wave complete in program order, so
-// the only ordering needed is the compiler's (signal fences).  Returns, in
-// lane 8q (q < 6), total q.
-__device__ __forceinline__ double wave_row_totals(const double m[kMomQ], double *lds, int lane) {
-#pragma unroll
-    for (int q = 0; q < kMomQ; ++q) lds[q * kLdsQStride + lane] = m[q];
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    const int qq = lane >> 3, part = lane & 7;
-    const double2 *src = reinterpret_cast<const double2 *>(lds + qq * kLdsQStride + part * 8);
-    const double2 x0 = src[0], x1 = src[1], x2 = src[2], x3 = src[3];
-    double s = ((x0.x + x0.y) + (x1.x + x1.y)) + ((x2.x + x2.y) + (x3.x + x3.y));
-    s += dpp_f64<0xB1, 0xF>(s);   // quad_perm [1,0,3,2]
-    s += dpp_f64<0x4E, 0xF>(s);   // quad_perm [2,3,0,1]
-    s += dpp_f64<0x141, 0xF>(s);  // row_half_mirror
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    return s;
-}
-__device__ __forceinline__ void wave_row_moments(const double m[kMomQ], double *lds, int lane, gdouble *dst) {
-    const double s = wave_row_totals(m, lds, lane);
-    if ((lane & 7) == 0 && (lane >> 3) < kMomQ) dst[lane >> 3] = s;
-}
-
-// A register copy the compiler cannot coalesce with its source (the output
-// operand is early-clobber, so it gets a register of its own).
-__device__ __forceinline__ double fresh_copy(double x) {
-    double y;
-    asm("v_mov_b64 %0, %1" : "=&v"(y) : "v"(x));
-    return y;
-}
-__device__ __forceinline__ float fresh_copy(float x) {
-    float y;
-    asm("v_mov_b32 %0, %1" : "=&v"(y) : "v"(x));
-    return y;
-}
-
 // Byte-offset loads and stores from a wave-uniform base: the per-lane offset
 // is 32 bits (planes are limited to 2^29 cells), so the address is formed by
 // the memory unit from a scalar base plus one VGPR.
@@ -277,6 +237,54 @@ __device__ __forceinline__ void st_nt(gchar *base, uint32_t off, T v) {
 template <typename T>
 __device__ __forceinline__ T ld_nt(const gchar *base, uint32_t off) {
     return __builtin_nontemporal_load(reinterpret_cast<const __attribute__((address_space(1))) T *>(base + off));
+}
+
+// Row totals of the six integrands over the 64 lanes of a wave (one row group
+// per wave) through the wave's LDS scratch: every lane stores its six values;
+// lane 8q + p adds the eight values of quantity q held by lanes 8p .. 8p+7;
+// three DPP steps combine the eight partial sums of q (every lane of the
+// eight ends with the same total) and lane 8q writes it.  The association
+// order is fixed.  LDS operations of one wave complete in program order, so
+// the only ordering needed is the compiler's (signal fences).  Returns, in
+// lane 8q (q < 6), total q.
+__device__ __forceinline__ double wave_row_totals(const double m[kMomQ], double *lds, int lane) {
+#pragma unroll
+    for (int q = 0; q < kMomQ; ++q) lds[q * kLdsQStride + lane] = m[q];
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const int qq = lane >> 3, part = lane & 7;
+    const double2 *src = reinterpret_cast<const double2 *>(lds + qq * kLdsQStride + part * 8);
+    const double2 x0 = src[0], x1 = src[1], x2 = src[2], x3 = src[3];
+    double s = ((x0.x + x0.y) + (x1.x + x1.y)) + ((x2.x + x2.y) + (x3.x + x3.y));
+    s += dpp_f64<0xB1, 0xF>(s);   // quad_perm [1,0,3,2]
+    s += dpp_f64<0x4E, 0xF>(s);   // quad_perm [2,3,0,1]
+    s += dpp_f64<0x141, 0xF>(s);  // row_half_mirror
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return s;
+}
+// dst is wave-uniform: the store takes it as a scalar base with a 32-bit lane
+// offset.  The empty asm keeps the compiler from folding the lane offset into a
+// per-lane 64-bit pointer that lives across the march (one that did was
+// spilled, and each reload waited for every store still in flight).
+__device__ __forceinline__ void wave_row_moments(const double m[kMomQ], double *lds, int lane, gdouble *dst) {
+    const double s = wave_row_totals(m, lds, lane);
+    if ((lane & 7) == 0 && (lane >> 3) < kMomQ) {
+        uint32_t off = (uint32_t)(lane >> 3) * 8u;
+        asm volatile("" : "+v"(off));
+        st<double>((gchar *)dst, off, s);
+    }
+}
+
+// A register copy the compiler cannot coalesce with its source (the output
+// operand is early-clobber, so it gets a register of its own).
+__device__ __forceinline__ double fresh_copy(double x) {
+    double y;
+    asm("v_mov_b64 %0, %1" : "=&v"(y) : "v"(x));
+    return y;
+}
+__device__ __forceinline__ float fresh_copy(float x) {
+    float y;
+    asm("v_mov_b32 %0, %1" : "=&v"(y) : "v"(x));
+    return y;
 }
 
 // Moment integrands of one species' four components for one bin: the
@@ -797,10 +805,16 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
 #pragma unroll
         for (int c = 0; c < NC; ++c) dst[c] = ld<TI>(xb + (size_t)c * pin, off);
     };
+    // pair 1: acc at the stage B row.  The FP32 form loads it with the other
+    // operands of its step, one step ahead into the alternating buffers; the
+    // FP64 form has no registers to spare for that and loads it at the start
+    // of its own step instead.
+    constexpr bool ACC_AHEAD = FORM == 1;
     struct Buf {
         TI nw[NC];     // X look-ahead row a + 2 dir
         double pv[2];  // lane-distributed moment partials of X row a
         double ya[NC]; // pair 1: y at row a (stage 3 combine)
+        double ac[NC]; // pair 1, FP32 form: acc at the stage B row
     };
     auto issue = [&](int s, Buf &b) {
         const int a = wrap_row(row_a(s), nz);
@@ -813,6 +827,12 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
             const uint32_t offa = (uint32_t)(ar * nv + jl) * 8u;
 #pragma unroll
             for (int c = 0; c < NC; ++c) b.ya[c] = ld_nt<double>(yb8 + (size_t)c * p64, offa);
+            if constexpr (ACC_AHEAD) {
+                const int br = s >= 4 && s < nsteps ? row_a(s) - 2 * dir : start;  // in [z0, z1)
+                const uint32_t offb = (uint32_t)(br * nv + jl) * 8u;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) b.ac[c] = ld_nt<double>(accb + (size_t)c * p64, offb);
+            }
         }
     };
 
@@ -833,15 +853,11 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
         hi = mudv * A2;
     };
 
-    // pair 1: acc at the stage B row of step s, loaded at the end of step s - 1
-    // (one buffer: it is consumed at the end of its step, then refilled).  The
-    // FP64 form has no registers to spare for it across steps and loads it at
-    // the start of its own step instead.
-    constexpr bool ACC_AHEAD = FORM == 1;
-    double abn[NC];  // the carried buffer (FP32 form)
+    // pair 1, FP64 form: acc at the stage B row of step s, loaded at the start
+    // of the step
     auto load_acc = [&](int s, double (&dst)[NC]) {
         if constexpr (PAIR == 1) {
-            const int br = s >= 4 ? row_a(s) - 2 * dir : start;  // stage B row (in [z0, z1) from s = 4)
+            const int br = s >= 4 && s < nsteps ? row_a(s) - 2 * dir : start;  // stage B row (in [z0, z1) from s = 4)
             const uint32_t offb = (uint32_t)(br * nv + jl) * 8u;
 #pragma unroll
             for (int c = 0; c < NC; ++c) dst[c] = ld_nt<double>(accb + (size_t)c * p64, offb);
@@ -851,7 +867,7 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
         const int a = row_a(s);
         double abl[NC];
         if (!ACC_AHEAD && s >= 4) load_acc(s, abl);
-        const double(&ab)[NC] = ACC_AHEAD ? abn : abl;
+        const double(&ab)[NC] = ACC_AHEAD ? b.ac : abl;
         // ---- stage A: Z row a
         auto win = [&](int c, int m) -> TI { return m < R - 1 ? xw[c][m] : b.nw[c]; };
         double adv[NC];
@@ -916,7 +932,6 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
         }
         if (s < 4) {
             slide_x();
-            if (ACC_AHEAD && s == 3) load_acc(4, abn);
             return;
         }
         // ---- stage B: output row b
@@ -963,7 +978,6 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
         species_moment_terms(o, ca, cb, v, mt);
         wave_row_moments(mt, lds, l, m_out + (((size_t)brow * vchunks + vc) * 2 + sp) * kMomQ);
         slide_x();
-        if (ACC_AHEAD && s + 1 < nsteps) load_acc(s + 1, abn);
     };
 
     // prologue: X rows a(0) - 2 dir .. a(0) + dir, then the loads of step 0,
@@ -988,11 +1002,16 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
 #pragma unroll
         for (int m = 0; m < R; ++m) zw[c][m] = 0.0;
     }
+    // The loads of the next step are issued unconditionally (past the last
+    // step they read rows nobody uses, at most five rows beyond the segment,
+    // which one periodic wrap keeps inside the grid since nz >= 5).  A
+    // conditional issue leaves a path without those loads, and the compiler's
+    // wait counts, merged over both paths, then wait for the loads just issued.
     for (int s = 0; s < nsteps; s += 2) {
-        if (s + 1 < nsteps) issue(s + 1, bufB);
+        issue(s + 1, bufB);
         compute(s, bufA, false);
         if (s + 1 >= nsteps) break;
-        if (s + 2 < nsteps) issue(s + 2, bufA);
+        issue(s + 2, bufA);
         compute(s + 1, bufB, true);
     }
 }
@@ -1215,16 +1234,15 @@ int batch_waves_per_cu(int scheme, int form, bool wave_rows) {
     return wave_rows ? batch_waves_per_cu_w<true>(scheme, form) : batch_waves_per_cu_w<false>(scheme, form);
 }
 
-bool pair_supported(const InstDesc &d) { return d.scheme == 0 && d.lr_log2 == 6 && 2 * d.vchunks <= 8; }
+bool pair_supported(const InstDesc &d) { return d.scheme == 0 && d.nz >= 5 && d.lr_log2 == 6 && 2 * d.vchunks <= 8; }
 
 namespace {
 template <int FORM, int PAIR>
 hipError_t launch_pair_t(const InstDesc &d, dim3 grid, dim3 block, size_t shm, hipStream_t st) {
     const int W = (int)block.x / kWave;  // moment parts per row, 2 vchunks
-    // mask-free copies in the FP32 form only (both masks in its second pair,
-    // the part masks in its first): elsewhere the registers they free are
-    // taken by a freer schedule, which spills
-    constexpr int kFull = FORM == 1 ? (PAIR == 1 ? 3 : 2) : 0;
+    // mask-free copies in the FP32 form's second pair only: elsewhere the
+    // registers they free are taken by a freer schedule, which spills
+    constexpr int kFull = FORM == 1 && PAIR == 1 ? 3 : 0;
     const bool full = kFull != 0 && d.nv % kWave == 0 && (W & (W - 1)) == 0;
     if (W <= 2) {
         if (full) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 1, kFull>), grid, block, shm, st, d);
