@@ -410,7 +410,11 @@ __device__ __forceinline__ void sum_row_parts_c(const double pv[2], double S[kMo
 // have v < 0, so that the window is in upwind order; FD waves of odd segments,
 // whose flux then takes its arguments in reverse, REV).  The flux produced at
 // each step is the one on the face ahead in the march, hence the sign of dzs.
-template <int SCHEME, int FORM, int STAGE, bool WR, bool MIX, bool REV>
+//
+// XP: a row has more than 16 moment parts (nv > 512), which lanes add up in a
+// loop.  Only that copy carries the loop: inside the march, the loop's extra
+// control flow made the compiler wait for the loads just issued.
+template <int SCHEME, int FORM, int STAGE, bool WR, bool MIX, bool REV, bool XP>
 __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q, int l, int dir, double *lds) {
     constexpr bool IN32 = FORM == 1 && STAGE == 2;  // Y3 of the FP32 form is stored in FP32
     using T = typename std::conditional<FORM == 0, double, float>::type;   // stencil arithmetic
@@ -460,7 +464,7 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     const size_t pout = plane * out_es;
     const gdouble *m_in = (const gdouble *)(STAGE == 0 ? d.mom[0] : STAGE == 1 ? d.mom[1] : STAGE == 2 ? d.mom[2] : d.mom[3]);
     gdouble *m_out = (gdouble *)(STAGE == 0 ? d.mom[1] : STAGE == 1 ? d.mom[2] : STAGE == 2 ? d.mom[3] : d.mom[0]);
-    const int nparts = 2 * vchunks;
+    const int nparts = WR ? 2 * vchunks : 2;  // without wave rows nv <= 32: one chunk
     // lane-distributed partial reads (one row group per wave): lane 16 g + p
     // reads parts p, p + 16, ... of quantities g and g + 3
     constexpr bool lanep = WR;
@@ -489,7 +493,7 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     // stage combine
     auto issue_side = [&](int k, double (&a0)[NC], double (&S)[kMomQ], double (&pv)[2]) {
         const int r = start + dir * k;
-        int irow = min(r, nz - 1);
+        int irow = min(max(r, 0), nz - 1);  // r < 0 only at k = nsteps (a load nobody uses)
         if constexpr (WR) irow = __builtin_amdgcn_readfirstlane(irow);
         const gdouble *mp = m_in + (size_t)irow * nparts * kMomQ;
         if constexpr (lanep) {
@@ -497,13 +501,15 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
             // parts are zeroed there), so nothing waits for these loads here
             pv[0] = mp[poff];
             pv[1] = mp[poff + 3];
-            for (int pb = kPartLanes; pb < nparts; pb += kPartLanes) {  // nv > 512 only
-                const int pq = pb + l % kPartLanes;
-                const bool on2 = l < 3 * kPartLanes && pq < nparts;
-                const int o2 = min(pq, nparts - 1) * kMomQ + pg;
-                const double x0 = mp[o2], x1 = mp[o2 + 3];
-                pv[0] += on2 ? x0 : 0.0;
-                pv[1] += on2 ? x1 : 0.0;
+            if constexpr (XP) {
+                for (int pb = kPartLanes; pb < nparts; pb += kPartLanes) {
+                    const int pq = pb + l % kPartLanes;
+                    const bool on2 = l < 3 * kPartLanes && pq < nparts;
+                    const int o2 = min(pq, nparts - 1) * kMomQ + pg;
+                    const double x0 = mp[o2], x1 = mp[o2 + 3];
+                    pv[0] += on2 ? x0 : 0.0;
+                    pv[1] += on2 ? x1 : 0.0;
+                }
             }
         } else {
 #pragma unroll
@@ -522,9 +528,10 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     // the window row entering at step k
     auto issue_ahead = [&](int k, TI (&nw)[NC]) {
         const int r = start + dir * k;
-        // WR: the look-ahead row lies in [z0 - AH, z1 - 1 + AH].  Otherwise rows
-        // past a ragged segment end are not produced and their look-ahead stays
-        // on the last produced row.  Both stay inside (-nz, 2 nz).
+        // WR: the look-ahead row lies in [z0 - 1 - AH, z1 + AH] (the ends at
+        // k = nsteps, loads nobody uses).  Otherwise rows past a ragged segment
+        // end are not produced and their look-ahead stays on the last produced
+        // row.  Both stay inside (-nz, 2 nz), since nz > AH + 1 for every scheme.
         const int ahead = WR ? r + dir * AH : min(r + AH, q.z1 - 1 + AH);
         load_row(wrap_row(ahead, nz), nw);
     };
@@ -638,11 +645,15 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         fprev[c] = interface_flux<SCHEME, MIX, T>(x(0), x(1), x(2), x(3), x(4), x(5), x(6), x(7), tv, vpos, cv, ce,
                                                   epsv);
     }
+    // The loads of the next step are issued unconditionally (at k = nsteps they
+    // read rows nobody uses, inside the grid): a conditional issue leaves a
+    // path without them, and the compiler's wait counts, merged over both
+    // paths, then wait for the loads just issued.
     for (int k = 0; k < nsteps; k += 2) {
-        if (k + 1 < nsteps) issue(k + 1, bufB);
+        issue(k + 1, bufB);
         compute(k, bufA);
         if (k + 1 >= nsteps) break;
-        if (k + 2 < nsteps) issue(k + 2, bufA);
+        issue(k + 2, bufA);
         compute(k + 1, bufB);
     }
 }
@@ -662,21 +673,25 @@ __device__ __forceinline__ void stage_group(const InstDesc &d, int task, int l, 
     const GroupGeom q = group_geom(d, task, l);
     if constexpr (WR) {
         if (q.z1 <= q.z0) return;  // wave-uniform
+        if (2 * d.vchunks > kPartLanes) {  // nv > 512: one copy, marching up with per-lane stencils (same fluxes)
+            stage_body<SCHEME, FORM, STAGE, true, SCHEME == 1, false, true>(d, q, l, 1, lds);
+            return;
+        }
         if constexpr (SCHEME == 1) {
             const double v = d.vel[q.jl];
             const bool any_pos = __ballot(q.lane_on && v > 0.0) != 0;
             const bool any_neg = __ballot(q.lane_on && v < 0.0) != 0;
             const int up = any_neg ? -1 : 1;
-            if (any_pos && any_neg) stage_body<SCHEME, FORM, STAGE, true, true, false>(d, q, l, 1, lds);
-            else if (kAltDir && (q.segi & 1)) stage_body<SCHEME, FORM, STAGE, true, false, true>(d, q, l, -up, lds);
-            else stage_body<SCHEME, FORM, STAGE, true, false, false>(d, q, l, up, lds);
+            if (any_pos && any_neg) stage_body<SCHEME, FORM, STAGE, true, true, false, false>(d, q, l, 1, lds);
+            else if (kAltDir && (q.segi & 1)) stage_body<SCHEME, FORM, STAGE, true, false, true, false>(d, q, l, -up, lds);
+            else stage_body<SCHEME, FORM, STAGE, true, false, false, false>(d, q, l, up, lds);
         } else if (kAltDir && (q.segi & 1)) {
-            stage_body<SCHEME, FORM, STAGE, true, false, true>(d, q, l, -1, lds);
+            stage_body<SCHEME, FORM, STAGE, true, false, true, false>(d, q, l, -1, lds);
         } else {
-            stage_body<SCHEME, FORM, STAGE, true, false, false>(d, q, l, 1, lds);
+            stage_body<SCHEME, FORM, STAGE, true, false, false, false>(d, q, l, 1, lds);
         }
     } else {
-        stage_body<SCHEME, FORM, STAGE, false, SCHEME == 1, false>(d, q, l, 1, lds);
+        stage_body<SCHEME, FORM, STAGE, false, SCHEME == 1, false, false>(d, q, l, 1, lds);
     }
 }
 
