@@ -192,3 +192,31 @@ def test_batch_mixes_every_variant():
                     s.set_fusion(False)
                     s.step(9)
                     assert np.array_equal(b.get_state(i), s.get_state()), (prec, i)
+
+
+MANY_BINS = [(wl.FD_KO, 513, 17, wl.FP64, o.QUAD_MIDPOINT), (wl.FV_WENO7, 700, 13, wl.FP64, o.QUAD_TRAPEZOID),
+             (wl.FD_KO, 1100, 10, wl.FP32_ACC64, o.QUAD_MIDPOINT), (wl.FV_WENO7, 1089, 11, wl.FP32_ACC64, o.QUAD_SIMPSON)]
+
+
+@pytest.mark.parametrize("scheme,nv,nz,prec,quad", MANY_BINS)
+def test_many_bins_more_than_16_moment_parts(scheme, nv, nz, prec, quad):
+    """nv > 512: a row has more than 16 moment parts (one per 64-bin chunk and
+    species), which the kernels sum in a copy of their own.  Against the oracle
+    from a random nonlinear state; bitwise the same at every launch shape and
+    inside a batch."""
+    w = wl.small_fd(9)
+    w.update(nz=nz, nv=nv, L=0.7 * nz, scheme=scheme, precision=prec, quadrature=quad, omega=0.2, lam=0.3,
+             alpha=0.9)
+    y0 = wl.random_unit_state(nz, nv, seed=nv)
+    print(f"many bins: scheme {scheme} nv {nv} nz {nz} form {prec} quadrature {quad}", flush=True)
+    got, info = run_gpu(w, 3, state=y0)
+    assert info["launches_per_step"] == 4
+    err = maxabs(got, run_oracle(w, 3, state=y0))
+    assert err <= (1e-12 if prec == wl.FP64 else 1e-5), err
+    for seg in (1, 4, nz):
+        alt, _ = run_gpu(w, 3, state=y0, seg=seg)
+        assert np.array_equal(alt, got), seg
+    with cosenu.Batch([w]) as b:
+        b.set_state(0, y0)
+        b.step(3)
+        assert np.array_equal(b.get_state(0), got)
