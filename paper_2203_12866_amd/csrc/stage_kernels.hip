@@ -1255,9 +1255,10 @@ namespace {
 template <int FORM, int PAIR>
 hipError_t launch_pair_t(const InstDesc &d, dim3 grid, dim3 block, size_t shm, hipStream_t st) {
     const int W = (int)block.x / kWave;  // moment parts per row, 2 vchunks
-    // mask-free copies in the FP32 form's second pair only: elsewhere the
-    // registers they free are taken by a freer schedule, which spills
-    constexpr int kFull = FORM == 1 && PAIR == 1 ? 3 : 0;
+    // mask-free copies in the FP32 form only (both masks in its second pair,
+    // the part masks in its first): elsewhere the registers they free are
+    // taken by a freer schedule, which spills
+    constexpr int kFull = FORM == 1 ? (PAIR == 1 ? 3 : 2) : 0;
     const bool full = kFull != 0 && d.nv % kWave == 0 && (W & (W - 1)) == 0;
     if (W <= 2) {
         if (full) hipLaunchKernelGGL((pair_kernel<FORM, PAIR, 1, kFull>), grid, block, shm, st, d);
