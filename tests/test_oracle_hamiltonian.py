@@ -113,6 +113,8 @@ def test_homogeneous_self_interaction_conserves_polarisation_length_to_fourth_or
         for base in (0, 4):
             P = pvec(y, base)
             d = max(d, np.abs(np.sqrt((P[1:] ** 2).sum(axis=0)) - 1.0).max())
+        # the oracle's own error measure dP_max (Sec. 5) is the same maximum
+        assert abs(o.diagnostics(p, y)["dP_max"] - d) < 1e-15
         drift.append(d)
     assert drift[0] > 1e-12
     assert abs(math.log2(drift[0] / drift[1]) - 4.0) < 0.3, drift
