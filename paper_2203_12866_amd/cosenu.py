@@ -134,6 +134,7 @@ def _lib():
             "cosenu_batch_time_steps": (ctypes.c_int, [vp, i64, dp]),
             "cosenu_batch_autotune": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
             "cosenu_batch_last_error": (ctypes.c_char_p, [vp]),
+            "cosenu_test_inject_failure": (ctypes.c_int, [i32, i32]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)

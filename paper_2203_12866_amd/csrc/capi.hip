@@ -2,7 +2,10 @@
 // and initial data (Sec. 3 and 5), device buffers, the per-step HIP graph,
 // diagnostics, timing and the launch-shape autotuner.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
+#include <stdexcept>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -13,6 +16,7 @@
 
 #include "cosenu.h"
 #include "cosenu_host.h"
+#include "cosenu_testing.h"
 #include "cosenu_internal.h"
 
 using namespace cosenu;
@@ -31,7 +35,37 @@ const char *strerror_code(int code) {
     }
 }
 
+int abi_fail(std::string *err, int code, const char *what) noexcept {
+    if (err) {
+        try {
+            *err = what ? what : "exception";
+        } catch (...) {
+        }
+    }
+    return code;
+}
+
+namespace {
+std::atomic<int> g_fail_site{0}, g_fail_after{0};
+}  // namespace
+
+bool test_fail_now(int site) {
+    if (g_fail_site.load() != site) return false;
+    if (g_fail_after.fetch_sub(1) > 0) return false;
+    g_fail_site.store(0);
+    return true;
+}
+
+bool hw_queues_below(int n) {
+    const char *e = std::getenv("GPU_MAX_HW_QUEUES");
+    if (!e || !*e) return false;
+    const long v = std::strtol(e, nullptr, 10);
+    return v > 0 && v < n;
+}
+
 std::string validate_params(const cosenu_params &p) {
+    if (test_fail_now(kFailThrowBadAlloc)) throw std::bad_alloc();
+    if (test_fail_now(kFailThrowOther)) throw std::runtime_error("injected exception (test hook)");
     char buf[256];
     auto fin = [](double x) { return std::isfinite(x); };
     if (p.scheme != COSENU_FD_KO && p.scheme != COSENU_FV_WENO7) return "scheme must be COSENU_FD_KO or COSENU_FV_WENO7";
@@ -467,9 +501,16 @@ extern "C" {
 
 const char *cosenu_strerror(int code) { return strerror_code(code); }
 
+int cosenu_test_inject_failure(int32_t site, int32_t after) {
+    if (site < 0 || site >= kFailSites || after < 0) return COSENU_EINVAL;
+    g_fail_after.store(after);
+    g_fail_site.store(site);
+    return COSENU_OK;
+}
+
 const char *cosenu_last_error(const cosenu_sim *s) { return s ? s->err.c_str() : "null handle"; }
 
-int cosenu_params_default(cosenu_params *p) {
+int cosenu_params_default(cosenu_params *p) try {
     if (!p) return COSENU_EINVAL;
     std::memset(p, 0, sizeof *p);
     p->nz = 512;
@@ -493,9 +534,9 @@ int cosenu_params_default(cosenu_params *p) {
     p->ko_order = 2;
     p->quadrature = COSENU_QUAD_MIDPOINT;
     return COSENU_OK;
-}
+} COSENU_ABI_CATCH(nullptr)
 
-void cosenu_destroy(cosenu_sim *s) {
+void cosenu_destroy(cosenu_sim *s) try {
     if (!s) return;
     if (s->own_stream) (void)hipStreamSynchronize(s->own_stream);
     if (s->stream && s->stream != s->own_stream) (void)hipStreamSynchronize(s->stream);
@@ -503,19 +544,23 @@ void cosenu_destroy(cosenu_sim *s) {
     for (void *p : s->allocs) (void)hipFree(p);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s;
+} catch (...) {
 }
 
-int cosenu_create(const cosenu_params *p, cosenu_sim **out) {
+int cosenu_create(const cosenu_params *p, cosenu_sim **out) try {
     if (!p || !out) return COSENU_EINVAL;
     *out = nullptr;
     if (!validate_params(*p).empty()) return COSENU_EINVAL;
     cosenu_sim *s = new (std::nothrow) cosenu_sim();
     if (!s) return COSENU_ENOMEM;
+    // destroys the partly built handle on every early return, and on an
+    // exception (which the ABI guard below then turns into a code)
+    struct Owner {
+        cosenu_sim *h;
+        ~Owner() { if (h) cosenu_destroy(h); }
+    } own{s};
     s->prm = *p;
-    auto fail = [&](int rc) {
-        cosenu_destroy(s);
-        return rc;
-    };
+    auto fail = [&](int rc) { return rc; };
     if (hipGetDevice(&s->device) != hipSuccess) return fail(COSENU_EDEVICE);
     if (hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking) != hipSuccess) return fail(COSENU_EDEVICE);
     s->stream = s->own_stream;
@@ -568,11 +613,12 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) {
         return fail(COSENU_EDEVICE);
     if ((rc = state_changed(s))) return fail(rc);
     if ((rc = build_graphs(s))) return fail(rc);
+    own.h = nullptr;
     *out = s;
     return COSENU_OK;
-}
+} COSENU_ABI_CATCH(nullptr)
 
-int cosenu_step(cosenu_sim *s, int64_t nsteps) {
+int cosenu_step(cosenu_sim *s, int64_t nsteps) try {
     SIM_CHECK(s);
     if (nsteps < 0) return COSENU_EINVAL;
     if (nsteps == 0) return COSENU_OK;
@@ -593,15 +639,15 @@ int cosenu_step(cosenu_sim *s, int64_t nsteps) {
     s->step += nsteps;
     s->t += (double)nsteps * s->d.dt;
     return COSENU_OK;
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_sync(cosenu_sim *s) {
+int cosenu_sync(cosenu_sim *s) try {
     SIM_CHECK(s);
     HIPCHK(s, hipStreamSynchronize(s->stream));
     return COSENU_OK;
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_get_state(cosenu_sim *s, double *out, size_t n) {
+int cosenu_get_state(cosenu_sim *s, double *out, size_t n) try {
     SIM_CHECK(s);
     const size_t need = (size_t)8 * s->d.nz * s->d.nv;
     if (!out || n < need) return COSENU_EINVAL;
@@ -609,46 +655,46 @@ int cosenu_get_state(cosenu_sim *s, double *out, size_t n) {
     HIPCHK(s, hipMemcpy2DAsync(out, row, s->d.y, s->d.ps * sizeof(double), row, 8, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     return COSENU_OK;
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_get_rows(cosenu_sim *s, int64_t z0, int32_t nrows, double *out, size_t n) {
+int cosenu_get_rows(cosenu_sim *s, int64_t z0, int32_t nrows, double *out, size_t n) try {
     SIM_CHECK(s);
     if (!out || nrows < 1 || nrows > s->d.nz || n < (size_t)8 * nrows * s->d.nv) return COSENU_EINVAL;
     HIPCHK(s, rows_to_host(s->d, z0, nrows, s->stream, out));
     return COSENU_OK;
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_set_state(cosenu_sim *s, const double *in, size_t n) {
+int cosenu_set_state(cosenu_sim *s, const double *in, size_t n) try {
     SIM_CHECK(s);
     const size_t need = (size_t)8 * s->d.nz * s->d.nv;
     if (!in || n < need) return COSENU_EINVAL;
     return upload_state(s, in);
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_set_clock(cosenu_sim *s, double t, int64_t step) {
+int cosenu_set_clock(cosenu_sim *s, double t, int64_t step) try {
     SIM_CHECK(s);
     if (!std::isfinite(t) || step < 0) return COSENU_EINVAL;
     s->t = t;
     s->step = step;
     return COSENU_OK;
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_moments(cosenu_sim *s, double *out, size_t n) {
+int cosenu_moments(cosenu_sim *s, double *out, size_t n) try {
     SIM_CHECK(s);
     if (!out || n < (size_t)8 * s->d.nz) return COSENU_EINVAL;
     HIPCHK(s, moments_to_host(s->d, s->mom_out, s->stream, out));
     return COSENU_OK;
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_conserved(cosenu_sim *s, cosenu_conserved_t *out) {
+int cosenu_conserved(cosenu_sim *s, cosenu_conserved_t *out) try {
     SIM_CHECK(s);
     if (!out) return COSENU_EINVAL;
     int rc = compute_conserved(s, out);
     if (rc) return rc;
     return out->nonfinite ? COSENU_ENONFINITE : COSENU_OK;
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_info(cosenu_sim *s, cosenu_info_t *out) {
+int cosenu_info(cosenu_sim *s, cosenu_info_t *out) try {
     SIM_CHECK(s);
     if (!out) return COSENU_EINVAL;
     std::memset(out, 0, sizeof *out);
@@ -666,16 +712,16 @@ int cosenu_info(cosenu_sim *s, cosenu_info_t *out) {
                           (double)s->d.nz * s->d.nv;
     out->launches_per_step = launches_per_step(s);
     return COSENU_OK;
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_set_stream(cosenu_sim *s, void *hip_stream) {
+int cosenu_set_stream(cosenu_sim *s, void *hip_stream) try {
     SIM_CHECK(s);
     HIPCHK(s, hipStreamSynchronize(s->stream));
     s->stream = hip_stream ? (hipStream_t)hip_stream : s->own_stream;
     return COSENU_OK;
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_set_seg_rows(cosenu_sim *s, int32_t seg_rows) {
+int cosenu_set_seg_rows(cosenu_sim *s, int32_t seg_rows) try {
     SIM_CHECK(s);
     if (seg_rows < 0) return COSENU_EINVAL;
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -686,17 +732,17 @@ int cosenu_set_seg_rows(cosenu_sim *s, int32_t seg_rows) {
     }
     set_shape(s->d, seg);
     return build_graphs(s);
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_set_fusion(cosenu_sim *s, int32_t on) {
+int cosenu_set_fusion(cosenu_sim *s, int32_t on) try {
     SIM_CHECK(s);
     if (on != 0 && on != 1) return COSENU_EINVAL;
     HIPCHK(s, hipStreamSynchronize(s->stream));
     s->fusion_wanted = on != 0;
     return build_graphs(s);
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_time_steps(cosenu_sim *s, int64_t nsteps, double *ms) {
+int cosenu_time_steps(cosenu_sim *s, int64_t nsteps, double *ms) try {
     SIM_CHECK(s);
     if (!ms || nsteps < 0) return COSENU_EINVAL;
     hipEvent_t a, b;
@@ -714,9 +760,9 @@ int cosenu_time_steps(cosenu_sim *s, int64_t nsteps, double *ms) {
     *ms = f;
     if (rc == COSENU_EDEVICE && s->err.empty()) s->err = "event timing failed";
     return rc;
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage) {
+int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage) try {
     SIM_CHECK(s);
     if (!ms_stage || nsteps < 0) return COSENU_EINVAL;
     std::vector<hipEvent_t> ev(8);
@@ -746,9 +792,9 @@ int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage) {
         s->err = "stage timing failed";
     }
     return rc;
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
-int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
+int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) try {
     SIM_CHECK(s);
     HIPCHK(s, hipStreamSynchronize(s->stream));
     // Stages 1..3 write only scratch (Y2, Y3, Y4, acc and the moments of
@@ -805,6 +851,6 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) {
     store_tuned_seg(s->d.scheme, s->prm.precision, s->prm.nz, s->prm.nv, fused(s), best);
     if (seg_rows) *seg_rows = best;
     return build_graphs(s);
-}
+} COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
 }  // extern "C"

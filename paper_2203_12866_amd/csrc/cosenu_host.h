@@ -1,6 +1,8 @@
 // Host-side helpers shared by the single-instance and batched runtimes.
 #pragma once
 
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -30,5 +32,34 @@ void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vect
 // tuned segment length per (kernel variant, form, nv, nz bucket) and path (fused stage pairs or single stages); 0 if none
 int tuned_seg(int scheme, int form, int nz, int nv, bool pairs);
 void store_tuned_seg(int scheme, int form, int nz, int nv, bool pairs, int seg);
+
+// ---- no C++ exception crosses the C ABI ------------------------------------
+// Every extern "C" entry point returning a code is a function-try-block that
+// ends in COSENU_ABI_CATCH(err): std::bad_alloc becomes COSENU_ENOMEM, any other
+// exception COSENU_EDEVICE, with a message kept in *err when a handle exists.
+int abi_fail(std::string *err, int code, const char *what) noexcept;
+#define COSENU_ABI_CATCH(errp)                                                                     \
+    catch (const std::bad_alloc &) {                                                               \
+        return ::cosenu::abi_fail((errp), COSENU_ENOMEM, "host allocation failed");                \
+    }                                                                                              \
+    catch (const std::exception &e_) {                                                             \
+        return ::cosenu::abi_fail((errp), COSENU_EDEVICE, e_.what());                              \
+    }                                                                                              \
+    catch (...) {                                                                                  \
+        return ::cosenu::abi_fail((errp), COSENU_EDEVICE, "unexpected C++ exception");             \
+    }
+
+// ---- failure injection for the test-suite (cosenu_testing.h) ---------------
+enum {
+    kFailThrowBadAlloc = 1,    // parameter validation throws std::bad_alloc
+    kFailThrowOther = 2,       // parameter validation throws std::runtime_error
+    kFailBatchBuildTasks = 3,  // a batch task-list rebuild returns COSENU_EDEVICE
+    kFailSites = 4
+};
+// true once, when the failure armed for this site is due
+bool test_fail_now(int site);
+
+// GPU_MAX_HW_QUEUES is set to a positive value below n
+bool hw_queues_below(int n);
 
 }  // namespace cosenu

@@ -11,13 +11,17 @@ from paper_2203_12866_amd import cosenu
 from paper_2203_12866_amd import workloads as wl
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "cosenu.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(cosenu_\w+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(cosenu_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_function():
@@ -101,3 +105,39 @@ def test_workloads_are_seeded_and_in_range():
         assert abs(w["L"] / w["nz"] - 0.09765625) < 1e-12
     p = cosenu.params_from(wl.fv_65536x256(3))
     assert (p.nz, p.nv, p.scheme, p.omega) == (65536, 256, 1, 1e-3)
+
+
+@pytest.mark.parametrize("site,code", [(1, cosenu.ENOMEM), (2, cosenu.EDEVICE)])
+def test_exceptions_become_codes(site, code):
+    """A C++ exception thrown inside the library (here injected in parameter
+    validation, before any device call) comes back as an error code from the
+    C entry point instead of terminating the process."""
+    L = cosenu.lib()
+    p = cosenu.default_params()
+    h = ctypes.c_void_p()
+    assert L.cosenu_test_inject_failure(site, 0) == 0
+    try:
+        assert L.cosenu_create(ctypes.byref(p), ctypes.byref(h)) == code
+        assert not h.value
+    finally:
+        L.cosenu_test_inject_failure(0, 0)
+    # the batch entry point, with the exception on its second instance
+    arr = (cosenu.Params * 3)(p, p, p)
+    assert L.cosenu_test_inject_failure(site, 1) == 0
+    try:
+        assert L.cosenu_batch_create(arr, 3, ctypes.byref(h)) == code
+        assert not h.value
+    finally:
+        L.cosenu_test_inject_failure(0, 0)
+
+
+def test_failure_injection_arguments():
+    L = cosenu.lib()
+    assert L.cosenu_test_inject_failure(99, 0) == cosenu.EINVAL
+    assert L.cosenu_test_inject_failure(1, -1) == cosenu.EINVAL
+    assert L.cosenu_test_inject_failure(0, 0) == 0
+    # disarmed: validation proceeds normally (an invalid nz is still EINVAL)
+    p = cosenu.default_params()
+    p.nz = 2
+    h = ctypes.c_void_p()
+    assert L.cosenu_create(ctypes.byref(p), ctypes.byref(h)) == cosenu.EINVAL

@@ -228,3 +228,38 @@ def test_degenerate_calls_are_no_ops_or_rejected():
         assert L.cosenu_batch_step(b._h, -1) == cosenu.EINVAL
         assert L.cosenu_batch_get_state(b._h, 2, p, buf.size) == cosenu.EINVAL
         assert L.cosenu_batch_get_state(b._h, 0, p, 8 * 40 * 70 - 1) == cosenu.EINVAL
+
+
+def test_batch_survives_failed_autotune():
+    """A task-list rebuild that fails half-way through cosenu_batch_autotune
+    (forced from the host) returns an error, and the batch then steps from its
+    original launch shapes with step graphs rebuilt: every instance, fused
+    pairs and single stages, still equals its solo run bitwise."""
+    L = cosenu.lib()
+    ws = [dict(wl.small_fd(11), nz=48, nv=70, L=40.0, precision=wl.FP32_ACC64),   # fused pairs
+          dict(wl.small_fv(12), nz=33, nv=20, L=30.0, precision=wl.FP32_ACC64),   # WENO7, nv <= 32
+          dict(wl.small_fd(13), nz=40, nv=96, L=35.0, precision=wl.FP32_ACC64, ko_order=3)]
+    solo = []
+    for w in ws:
+        with cosenu.Sim(w) as s:
+            s.step(5)
+            solo.append(s.get_state())
+    with cosenu.Batch(ws) as b:
+        b.step(2)
+        segs0 = [b.info(i)["seg_rows"] for i in range(len(ws))]
+        assert L.cosenu_test_inject_failure(3, 2) == 0  # the third rebuild of the tuning loop fails
+        try:
+            rc = L.cosenu_batch_autotune(b._h, None)
+        finally:
+            L.cosenu_test_inject_failure(0, 0)
+        assert rc == cosenu.EDEVICE
+        assert "injected" in L.cosenu_batch_last_error(b._h).decode()
+        assert [b.info(i)["seg_rows"] for i in range(len(ws))] == segs0
+        b.step(3)
+        for i in range(len(ws)):
+            assert np.array_equal(b.get_state(i), solo[i]), i
+        # a later autotune succeeds and changes nothing in the results
+        b.autotune()
+        b.step(0)
+        for i in range(len(ws)):
+            assert np.array_equal(b.get_state(i), solo[i]), i
