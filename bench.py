@@ -1,12 +1,16 @@
 #!/usr/bin/env python3
 """Throughput of the RK4 hot path on one MI355X.
 
-A "step" is one classic RK4 step (4 stage launches) over the whole grid of
-the workload; the metric is cell-velocity-stage updates per second
-(nz * nv * 4 per step) plus the HBM bandwidth those updates imply.  The
-default workload is FD + Kreiss-Oliger on 16384 x 128 cells (L = 1600,
-ELN-crossing Gaussian family, alpha drawn from the seed), run in the
-FP32-with-FP64-accumulation form (headline) and in the FP64 form.
+A "step" is one classic RK4 step over the whole grid of the workload (four
+stage launches, or two fused stage-pair launches); the metric is
+cell-velocity-stage updates per second (nz * nv * 4 per step) plus the HBM
+bandwidth those updates imply.  The default (headline) workload is the
+largest single-GPU configuration: WENO7 on 2^20 x 512 cells (L = 1e5,
+omega = 1e-3, lambda = 10, ELN-crossing Gaussian family), in the
+FP32-with-FP64-accumulation form, with its FP64 twin beside it.  The same line
+carries, as secondary entries, WENO7 on 65536 x 256 in both forms and the
+batch of 64 uneven instances, each with its roofline, and a copy-bandwidth
+ceiling measured in the same run.
 
 Output: one JSON line on stdout.  Inputs are resident in HBM before the
 timed region starts.  --gpus N with N > 1 exits: the library runs on one GPU.
@@ -31,6 +35,11 @@ WORKLOADS = {
     "fd_ko_512x32": lambda prec: dict(__import__("paper_2203_12866_amd.workloads", fromlist=["x"]).small_fd(1), precision=prec),
 }
 FORMS = {"fp32acc": 1, "fp64": 0}
+DEFAULT_WORKLOAD = "fv_weno7_1048576x512"
+# grids above this many cells are compared between forms on slabs (cosenu_get_rows)
+# instead of whole states copied to the host
+SLAB_CELLS = 1 << 26
+SLAB_ROWS = 2048
 KERNEL_SOURCES = ("paper_2203_12866_amd/csrc/stage_kernels.hip",)
 
 
@@ -78,6 +87,15 @@ def tracked(w, c0, c1):
             "rel_drift": {k: v / scale for k, v in d.items()}}
 
 
+def _slab_starts(w):
+    """Three slab positions: the perturbation at the domain centre, the periodic
+    seam, and a seeded random place."""
+    import numpy as np
+    nz = w["nz"]
+    rng = np.random.default_rng(12345)
+    return [nz // 2 - SLAB_ROWS // 2, nz - SLAB_ROWS // 2, int(rng.integers(0, nz))]
+
+
 def run_form(cosenu, torch, w, steps, warmup, seg, stage_steps, fused=True):
     sim = cosenu.Sim(w)
     c0 = sim.conserved()
@@ -95,7 +113,10 @@ def run_form(cosenu, torch, w, steps, warmup, seg, stage_steps, fused=True):
     wall = time.perf_counter() - t0
     stage_ms = sim.time_stages(stage_steps)  # one event pair around every stage launch
     info = sim.info()
-    state = sim.get_state()
+    if w["nz"] * w["nv"] > SLAB_CELLS:
+        state = {z0: sim.get_rows(z0, SLAB_ROWS) for z0 in _slab_starts(w)}
+    else:
+        state = sim.get_state()
     track = tracked(w, c0, sim.conserved())
     sim.close()
     cells = w["nz"] * w["nv"]
@@ -110,6 +131,54 @@ def run_form(cosenu, torch, w, steps, warmup, seg, stage_steps, fused=True):
                 launch_s=launch_s,
                 stage_us=[m * 1e3 / stage_steps for m in stage_ms[:nl]],
                 achieved_gbps=info["bytes_per_step"] / nl / launch_s / 1e9)
+
+
+def form_difference(a, b):
+    """FP32-form minus FP64-form state: max-abs over everything, and the
+    off-diagonal planes relative to their largest magnitude (whole states, or
+    the same slabs of both)."""
+    import numpy as np
+    if isinstance(a, dict):
+        a = np.concatenate([a[k] for k in sorted(a)], axis=1)
+        b = np.concatenate([b[k] for k in sorted(b)], axis=1)
+    off = [2, 3, 6, 7]
+    return {"max_abs": float(np.abs(a - b).max()),
+            "max_rel_offdiag": float(np.abs(a[off] - b[off]).max() / max(np.abs(b[off]).max(), 1e-300))}
+
+
+def copy_ceiling(torch, gib=2, reps=10):
+    """Device-to-device copy bandwidth (bytes read + written per second) of a
+    torch copy of `gib` GiB, timed with events on torch's stream: the practical
+    streaming ceiling of this GPU, measured in the same run."""
+    n = (gib << 30) // 4
+    a = torch.ones(n, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    gbps = 2.0 * a.numel() * a.element_size() * reps / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"gbps": gbps, "what": f"torch device copy of {gib} GiB, {reps} repetitions (read + write bytes)"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def _oracle_sample(o, w, rows, steps):
@@ -164,6 +233,7 @@ def cpu_baseline(cosenu, w, budget_s):
     finally:
         o.set_num_threads(threads)
     cb = {"value": rate, "unit": "cell·v·stage updates/s", "cores": threads, "kind": "oracle",
+          "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
           "sample": f"FP64 oracle, {threads} threads: {sample}",
           "one_core": {"value": r1, "cores": 1,
                        "sample": f"1 RK4 step of a periodic {rows1}x{nv} z-slab, 1 thread, {t1:.1f} s"}}
@@ -203,44 +273,106 @@ def run_batch(cosenu, torch, insts, steps, warmup):
                 segs=segs, tune_s=tune_s, nonfinite=bad)
 
 
+def batch_summary(r, insts, steps):
+    n_fd = sum(1 for w in insts if w["scheme"] == 0)
+    return {
+        "value": r["updates"], "unit": "cell·v·stage updates/s", "steps": steps,
+        "ms_per_step": r["wall"] * 1e3 / steps,
+        "config": {"workload": "batch_64", "instances": len(insts), "fd_ko": n_fd, "fv_weno7": len(insts) - n_fd,
+                   "cells": r["cells"], "nz_range": [min(w["nz"] for w in insts), max(w["nz"] for w in insts)],
+                   "nv_set": sorted({w["nv"] for w in insts}), "form": "FP32 stencils, FP64 moments/commutator/RK4",
+                   "seg_rows_per_variant": {k: v for k, v in zip(BATCH_VARIANTS, r["segs"]) if v},
+                   "fused_pair_instances": r["fused"]},
+        "modelled_gbps": r["gbps_model"],
+        "bytes_per_update": r["bytes_step"] / (r["cells"] * 4.0),
+        # the variants' launch chains overlap, so there is no single launch
+        # duration: the whole step's algorithmic bytes over its graph time
+        "roofline": {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": r["achieved_gbps"] / PEAK_HBM_GBPS,
+                     "traffic": measured_traffic("batch_64", "fp32acc"),
+                     "kernel": "batch_pair_kernel (FD fused pairs) and batch_stage_kernel (WENO7, FD nv<=32), "
+                               "one launch chain per variant, concurrent graph branches",
+                     "step_us": r["ev_ms"] * 1e3 / steps},
+        "nonfinite_instances": r["nonfinite"],
+        "autotune_s": r["tune_s"],
+    }
+
+
 def batch_main(args, cosenu, torch):
     from paper_2203_12866_amd import workloads as wl
     insts = wl.batch_64(4)
     r = run_batch(cosenu, torch, insts, args.steps, args.warmup)
     print(f"[bench] batch_64 fp32acc: {r['updates']:.4e} upd/s, {r['gbps_model']:.0f} GB/s modelled, "
           f"segments per variant {r['segs']} tuned in {r['tune_s']:.1f} s", file=sys.stderr, flush=True)
-    n_fd = sum(1 for w in insts if w["scheme"] == 0)
-    out = {
-        "metric": METRIC, "value": r["updates"], "unit": "cell·v·stage updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["wall"] * 1e3 / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64acc",
-        "data": "synthetic",
-        "config": {"workload": "batch_64", "instances": len(insts), "fd_ko": n_fd, "fv_weno7": len(insts) - n_fd,
-                   "cells": r["cells"], "nz_range": [min(w["nz"] for w in insts), max(w["nz"] for w in insts)],
-                   "nv_set": sorted({w["nv"] for w in insts}), "form": "FP32 stencils, FP64 moments/commutator/RK4",
-                   "seg_rows_per_variant": {k: v for k, v in zip(BATCH_VARIANTS, r["segs"]) if v},
-                   "fused_pair_instances": r["fused"]},
-        "hbm_gbps": r["gbps_model"],
-        "bytes_per_update": r["bytes_step"] / (r["cells"] * 4.0),
-        "roofline": {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": r["achieved_gbps"] / PEAK_HBM_GBPS, "traffic": None,
-                     "kernel": "batch_pair_kernel (FD fused pairs) and batch_stage_kernel (WENO7, FD nv<=32), "
-                               "one launch chain per variant, concurrent graph branches",
-                     "avg_launch_us": r["launch_s"] * 1e6},
-        "nonfinite_instances": r["nonfinite"],
-    }
+    b = batch_summary(r, insts, args.steps)
+    out = {"metric": METRIC, "value": b["value"], "unit": b["unit"], "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": b["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64acc", "data": "synthetic"}
+    out.update({k: v for k, v in b.items() if k not in out})
     print(json.dumps(out), flush=True)
+
+
+def kernel_name(w, pairs, form):
+    f = "FP32acc" if form == "fp32acc" else "FP64"
+    if pairs:
+        return f"pair_kernel<FD,{f}> (stages 1+2 and 3+4 fused)"
+    return f"stage_kernel<FD,{f}>" if w["scheme"] == 0 else f"stage_kernel<WENO7,{f}>"
+
+
+def run_workload(cosenu, torch, name, steps, warmup, seg, stage_steps, fused):
+    """Both forms of one workload: per-form throughput, the roofline of its
+    dominant kernel, the FP32-form / FP64-form difference and the tracked
+    quantities."""
+    mk = WORKLOADS[name]
+    res = {}
+    for form, prec in FORMS.items():
+        res[form] = run_form(cosenu, torch, mk(prec), steps, warmup, seg, stage_steps, fused=fused)
+        print(f"[bench] {name} {form}: {res[form]['updates']:.4e} upd/s, "
+              f"{res[form]['gbps_model']:.0f} GB/s modelled, seg {res[form]['seg']}, "
+              f"{res[form]['launches']} launches/step", file=sys.stderr, flush=True)
+    w = mk(1)
+    cells = w["nz"] * w["nv"]
+    forms = {}
+    for form, r in res.items():
+        pairs = r["launches"] == 2
+        forms[form] = {
+            "value": r["updates"], "ms_per_step": r["wall"] * 1e3 / steps, "modelled_gbps": r["gbps_model"],
+            "bytes_per_update": r["info"]["bytes_per_step"] / (cells * 4.0),
+            "roofline": {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                         "frac": r["achieved_gbps"] / PEAK_HBM_GBPS,
+                         "traffic": measured_traffic(name, form + ("/pairs" if pairs else "")),
+                         "kernel": kernel_name(w, pairs, form), "launches_per_step": r["launches"],
+                         "avg_launch_us": r["launch_s"] * 1e6, "launch_us_eager": r["stage_us"]},
+            "seg_rows": r["seg"],
+        }
+    return {
+        "config": {"workload": name, "nz": w["nz"], "nv": w["nv"], "L": w["L"], "cfl": w["cfl"],
+                   "scheme": "FD+KO" if w["scheme"] == 0 else "FV+WENO7", "alpha": w["alpha"],
+                   "omega": w["omega"], "lambda": w["lam"], "steps": steps},
+        "forms": forms,
+        "fp32_speedup_over_fp64": res["fp32acc"]["updates"] / res["fp64"]["updates"],
+        "fp32_vs_fp64_after_run": dict(form_difference(res["fp32acc"]["state"], res["fp64"]["state"]),
+                                       compared="whole state" if cells <= SLAB_CELLS else
+                                       f"3 slabs of {SLAB_ROWS} rows (centre, periodic seam, random)"),
+        "tracked": {"fp32acc": res["fp32acc"]["tracked"], "fp64": res["fp64"]["tracked"],
+                    "drift_ratio_fp32_over_fp64": res["fp32acc"]["tracked"]["max_rel_drift"] /
+                    max(res["fp64"]["tracked"]["max_rel_drift"], 1e-300)},
+        "_res": res,
+    }
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="fd_ko_16384x128", choices=sorted(WORKLOADS) + ["batch_64"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + ["batch_64"])
     ap.add_argument("--seg-rows", type=int, default=None, help="fixed launch shape (default: autotune)")
-    ap.add_argument("--stage-steps", type=int, default=50, help="steps timed launch by launch (eager, per-stage breakdown)")
+    ap.add_argument("--stage-steps", type=int, default=3, help="steps timed launch by launch (eager, per-stage breakdown)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary workloads (WENO7 65536x256 and the 64-instance batch)")
+    ap.add_argument("--secondary-steps", type=int, default=200, help="timed steps of the secondary workloads")
     ap.add_argument("--no-fusion", action="store_true", help="four single-stage launches per step")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -268,30 +400,17 @@ def main():
         return
     if args.workload == "batch_64":
         return batch_main(args, cosenu, torch)
-    mk = WORKLOADS[args.workload]
-    res = {}
-    for form, prec in FORMS.items():
-        res[form] = run_form(cosenu, torch, mk(prec), args.steps, args.warmup, args.seg_rows, args.stage_steps,
-                             fused=not args.no_fusion)
-        print(f"[bench] {args.workload} {form}: {res[form]['updates']:.4e} upd/s, "
-              f"{res[form]['gbps_model']:.0f} GB/s modelled, seg {res[form]['seg']}, "
-              f"{res[form]['launches']} launches/step", file=sys.stderr, flush=True)
-    single = None
-    if res["fp32acc"]["launches"] == 2:  # the same form on four single-stage launches, for comparison
-        single = run_form(cosenu, torch, mk(1), args.steps, args.warmup, args.seg_rows, args.stage_steps, fused=False)
-        print(f"[bench] {args.workload} fp32acc single stages: {single['updates']:.4e} upd/s", file=sys.stderr,
-              flush=True)
-
+    ceiling = copy_ceiling(torch)
+    print(f"[bench] copy ceiling {ceiling['gbps']:.0f} GB/s", file=sys.stderr, flush=True)
+    main_run = run_workload(cosenu, torch, args.workload, args.steps, args.warmup, args.seg_rows, args.stage_steps,
+                            not args.no_fusion)
+    res = main_run.pop("_res")
     head = res["fp32acc"]
-    w = mk(1)
-    pairs = head["launches"] == 2
-    kname = ("pair_kernel<FD,FP32acc> (stages 1+2 and 3+4 fused)" if pairs else
-             "stage_kernel<FD,FP32acc>" if w["scheme"] == 0 else "stage_kernel<WENO7,FP32acc>")
-    a, b = res["fp32acc"]["state"], res["fp64"]["state"]
-    fp32_vs_fp64 = {
-        "max_abs": float(np.abs(a - b).max()),
-        "max_rel_offdiag": float(np.abs(a[2:4] - b[2:4]).max() / max(np.abs(b[2:4]).max(), 1e-300)),
-    }
+    hf = main_run["forms"]["fp32acc"]
+    w = WORKLOADS[args.workload](1)
+    roof = dict(hf["roofline"])
+    roof["stream_ceiling"] = ceiling["gbps"]
+    roof["frac_of_stream_ceiling"] = roof["achieved"] / ceiling["gbps"]
     out = {
         "metric": METRIC,
         "value": head["updates"],
@@ -305,51 +424,42 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64acc",
         "data": "synthetic",
-        "config": {"workload": args.workload, "nz": w["nz"], "nv": w["nv"], "L": w["L"], "cfl": w["cfl"],
-                   "scheme": "FD+KO" if w["scheme"] == 0 else "FV+WENO7", "alpha": w["alpha"],
-                   "omega": w["omega"], "lambda": w["lam"], "form": "FP32 stencils, FP64 moments/commutator/RK4",
-                   "seg_rows": head["seg"]},
-        "hbm_gbps": head["gbps_model"],
-        "bytes_per_update": head["info"]["bytes_per_step"] / (w["nz"] * w["nv"] * 4.0),
-        "roofline": {
-            "bound": "hbm",
-            "achieved": head["achieved_gbps"],
-            "peak": PEAK_HBM_GBPS,
-            "unit": "GB/s",
-            "frac": head["achieved_gbps"] / PEAK_HBM_GBPS,
-            "traffic": measured_traffic(args.workload, "fp32acc" + ("/pairs" if pairs else "")),
-            "kernel": kname,
-            "launches_per_step": head["launches"],
-            "avg_launch_us": head["launch_s"] * 1e6,
-            "launch_us_eager": head["stage_us"],
-        },
-        "fp64_form": {
-            "value": res["fp64"]["updates"],
-            "ms_per_step": res["fp64"]["wall"] * 1e3 / args.steps,
-            "hbm_gbps": res["fp64"]["gbps_model"],
-            "bytes_per_update": res["fp64"]["info"]["bytes_per_step"] / (w["nz"] * w["nv"] * 4.0),
-            "roofline_achieved_gbps": res["fp64"]["achieved_gbps"],
-            "roofline_frac": res["fp64"]["achieved_gbps"] / PEAK_HBM_GBPS,
-            "avg_launch_us": res["fp64"]["launch_s"] * 1e6,
-            "launch_us_eager": res["fp64"]["stage_us"],
-            "launches_per_step": res["fp64"]["launches"],
-            "seg_rows": res["fp64"]["seg"],
-        },
-        "fp32_speedup_over_fp64": head["updates"] / res["fp64"]["updates"],
-        "fp32_vs_fp64_after_run": fp32_vs_fp64,
-        "tracked": {"fp32acc": res["fp32acc"]["tracked"], "fp64": res["fp64"]["tracked"],
-                    "drift_ratio_fp32_over_fp64": res["fp32acc"]["tracked"]["max_rel_drift"] /
-                    max(res["fp64"]["tracked"]["max_rel_drift"], 1e-300)},
+        "config": dict(main_run["config"], form="FP32 stencils, FP64 moments/commutator/RK4", seg_rows=head["seg"]),
+        "modelled_gbps": hf["modelled_gbps"],
+        "bytes_per_update": hf["bytes_per_update"],
+        "roofline": roof,
+        "copy_ceiling": ceiling,
+        "fp64_form": main_run["forms"]["fp64"],
+        "fp32_speedup_over_fp64": main_run["fp32_speedup_over_fp64"],
+        "fp32_vs_fp64_after_run": main_run["fp32_vs_fp64_after_run"],
+        "tracked": main_run["tracked"],
     }
-    if single is not None:
+    if res["fp32acc"]["launches"] == 2:  # the same form on four single-stage launches, for comparison
+        single = run_form(cosenu, torch, WORKLOADS[args.workload](1), args.steps, args.warmup, args.seg_rows,
+                          args.stage_steps, fused=False)
+        print(f"[bench] {args.workload} fp32acc single stages: {single['updates']:.4e} upd/s", file=sys.stderr,
+              flush=True)
         out["fp32acc_single_stages"] = {
             "value": single["updates"], "ms_per_step": single["wall"] * 1e3 / args.steps,
             "bytes_per_update": single["info"]["bytes_per_step"] / (w["nz"] * w["nv"] * 4.0),
             "roofline_achieved_gbps": single["achieved_gbps"], "seg_rows": single["seg"],
             "bitwise_equal_to_fused": bool(np.array_equal(single["state"], head["state"])),
         }
+    del res, head
+    if not args.no_secondary and args.workload == DEFAULT_WORKLOAD:
+        sec = {}
+        name = "fv_weno7_65536x256"
+        r3 = run_workload(cosenu, torch, name, args.secondary_steps, args.warmup, None, args.stage_steps, True)
+        r3.pop("_res")
+        sec[name] = r3
+        from paper_2203_12866_amd import workloads as wl
+        insts = wl.batch_64(4)
+        rb = run_batch(cosenu, torch, insts, args.secondary_steps, args.warmup)
+        print(f"[bench] batch_64 fp32acc: {rb['updates']:.4e} upd/s", file=sys.stderr, flush=True)
+        sec["batch_64"] = batch_summary(rb, insts, args.secondary_steps)
+        out["secondary"] = sec
     if not args.no_cpu_baseline:
-        cb, errs = cpu_baseline(cosenu, mk(0), args.cpu_budget)
+        cb, errs = cpu_baseline(cosenu, WORKLOADS[args.workload](0), args.cpu_budget)
         out["cpu_baseline"] = cb
         if errs is not None:
             out["error_vs_oracle"] = errs

@@ -63,10 +63,9 @@ bool hw_queues_below(int n) {
     return v > 0 && v < n;
 }
 
-std::string validate_params(const cosenu_params &p) {
-    if (test_fail_now(kFailThrowBadAlloc)) throw std::bad_alloc();
-    if (test_fail_now(kFailThrowOther)) throw std::runtime_error("injected exception (test hook)");
-    char buf[256];
+// The checks of every entry point that takes parameters, without allocating:
+// nullptr if p is valid, else the reason (a literal, or formatted into buf).
+const char *params_problem(const cosenu_params &p, char *buf, size_t nbuf) {
     auto fin = [](double x) { return std::isfinite(x); };
     if (p.scheme != COSENU_FD_KO && p.scheme != COSENU_FV_WENO7) return "scheme must be COSENU_FD_KO or COSENU_FV_WENO7";
     if (p.precision != COSENU_FP64 && p.precision != COSENU_FP32_ACC64) return "precision must be COSENU_FP64 or COSENU_FP32_ACC64";
@@ -76,7 +75,7 @@ std::string validate_params(const cosenu_params &p) {
         return "quadrature must be COSENU_QUAD_MIDPOINT, COSENU_QUAD_TRAPEZOID or COSENU_QUAD_SIMPSON";
     const int nzmin = p.scheme == COSENU_FD_KO ? std::max(5, 2 * p.ko_order + 1) : 9;
     if (p.nz < nzmin) {
-        snprintf(buf, sizeof buf, "nz = %d is below the stencil width (%d)", p.nz, nzmin);
+        snprintf(buf, nbuf, "nz = %d is below the stencil width (%d)", p.nz, nzmin);
         return buf;
     }
     if (p.nv < 2) return "nv must be >= 2 (with one bin max|v| = 0 and dt is undefined)";
@@ -92,7 +91,15 @@ std::string validate_params(const cosenu_params &p) {
     if (!fin(p.phase)) return "phase must be finite";
     if (!(fin(p.ko_eps) && p.ko_eps >= 0)) return "ko_eps must be >= 0";
     if (!(fin(p.weno_eps) && p.weno_eps > 0)) return "weno_eps must be > 0";
-    return "";
+    return nullptr;
+}
+
+std::string validate_params(const cosenu_params &p) {
+    if (test_fail_now(kFailThrowBadAlloc)) throw std::bad_alloc();
+    if (test_fail_now(kFailThrowOther)) throw std::runtime_error("injected exception (test hook)");
+    char buf[256];
+    const char *why = params_problem(p, buf, sizeof buf);
+    return why ? std::string(why) : std::string();
 }
 
 // Velocity grid spacing: bins of width 2/nv, or nv vertices spanning [-1, 1].

@@ -13,6 +13,7 @@ namespace cosenu {
 
 const char *strerror_code(int code);
 std::string validate_params(const cosenu_params &p);
+const char *params_problem(const cosenu_params &p, char *buf, size_t nbuf);
 double grid_dv(int nv, int quad);
 std::vector<double> bin_velocities(int nv, int quad);
 std::vector<double> quadrature_weights(int nv, int quad);
