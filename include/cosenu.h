@@ -237,6 +237,37 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows);
 const char *cosenu_strerror(int code);
 const char *cosenu_last_error(const cosenu_sim *s);
 
+/* ---- for callers that cannot allocate -------------------------------------
+ * cosenu_step_noalloc is for callers that must not allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It advances a state the caller owns on the device by nsteps RK4
+ * steps, exactly as cosenu_step advances a handle created from *p (same
+ * kernels, same launch shapes: fused stage pairs where the shape allows them;
+ * same arithmetic, so the same results bit for bit).  Every intermediate
+ * buffer (stage values, the accumulator, the angular-moment partials of
+ * each stage input, the per-point constants) lives in one static device
+ * array of COSENU_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from
+ * its first use on that GPU until the process ends.  The call allocates
+ * nothing on the device or the host.
+ *  p        problem (validated as by cosenu_create; pert_* and phase unused).
+ *  state    device pointer to the FP64 state [8][nz][nv] (layout as above,
+ *           planes contiguous, 8*nz*nv doubles), read at the start and
+ *           overwritten with the state after nsteps steps.  Caller-owned.
+ *  nsteps   >= 0; 0 returns at once.
+ *  hip_stream  HIP stream to enqueue on (NULL: the default stream).  The call
+ *           is asynchronous: it returns once the launches are enqueued.
+ * Needed scratch: about 8*nz*nv*(16 + 8 or 4 bytes: FP64 or FP32 form) plus
+ * 384*nz*ceil(nv/64) + 32*nv bytes (each part rounded up to 256 bytes); a
+ * problem needing more than COSENU_NOALLOC_SCRATCH_BYTES returns COSENU_EINVAL
+ * before anything is enqueued (for example 2048 x 128 fits, 4096 x 128 does
+ * not).  Invalid parameters also give COSENU_EINVAL; a HIP error COSENU_EDEVICE.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (other threads, or other streams not ordered with this one) race and
+ * corrupt each other's results.  Nothing in the array needs to start at zero:
+ * every value is written before it is read within one call.  */
+#define COSENU_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int cosenu_step_noalloc(const cosenu_params *p, double *state, int64_t nsteps, void *hip_stream);
+
 /* ---- batched execution ----------------------------------------------------
  * n independent simulations of any sizes and schemes (one precision for the
  * whole batch, taken from p[0]) advanced together: per RK4 step, each kernel

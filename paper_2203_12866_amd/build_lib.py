@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcosenu.so")
-SOURCES = ["stage_kernels.hip", "diag_kernels.hip", "capi.hip", "batch.hip"]
+SOURCES = ["stage_kernels.hip", "diag_kernels.hip", "capi.hip", "batch.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
@@ -47,7 +47,7 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd))
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

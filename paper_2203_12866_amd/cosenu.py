@@ -135,6 +135,7 @@ def _lib():
             "cosenu_batch_autotune": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
             "cosenu_batch_last_error": (ctypes.c_char_p, [vp]),
             "cosenu_test_inject_failure": (ctypes.c_int, [i32, i32]),
+            "cosenu_step_noalloc": (ctypes.c_int, [PP, vp, i64, vp]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -285,6 +286,18 @@ class Sim:
         seg = ctypes.c_int32()
         self._check(_lib().cosenu_autotune(self._h, ctypes.byref(seg)), "cosenu_autotune")
         return seg.value
+
+
+def step_noalloc(params: Params | dict, state_ptr: int, nsteps: int, hip_stream: int | None = None):
+    """cosenu_step_noalloc: nsteps RK4 steps of a caller-owned FP64 device state
+    [8][nz][nv] at address state_ptr (for example a torch tensor's data_ptr()),
+    with the library's static scratch array instead of allocations; enqueued on
+    hip_stream (None: the default stream), asynchronous."""
+    p = params if isinstance(params, Params) else params_from(params)
+    rc = _lib().cosenu_step_noalloc(ctypes.byref(p), ctypes.c_void_p(int(state_ptr)), int(nsteps),
+                                    ctypes.c_void_p(hip_stream or 0))
+    if rc:
+        raise CosenuError(rc, "cosenu_step_noalloc")
 
 
 class Batch:

@@ -105,61 +105,76 @@ std::string validate_params(const cosenu_params &p) {
 // Velocity grid spacing: bins of width 2/nv, or nv vertices spanning [-1, 1].
 double grid_dv(int nv, int quad) { return quad == COSENU_QUAD_MIDPOINT ? 2.0 / nv : 2.0 / (nv - 1); }
 
-// Bin midpoints v_j = -1 + (j + 1/2) dv (Sec. 3), or vertices v_j = -1 + j dv
+// Bin midpoint v_j = -1 + (j + 1/2) dv (Sec. 3), or vertex v_j = -1 + j dv
 // (Sec. 3.1).
+double point_velocity(int nv, int quad, int j) {
+    const double first = quad == COSENU_QUAD_MIDPOINT ? 0.5 : 0.0;
+    return -1.0 + (j + first) * grid_dv(nv, quad);
+}
+
+// Quadrature weight of point j in the velocity integral (Sec. 3 and 3.1): dv
+// per bin (Riemann sum), the composite trapezoid rule (ends halved) or the
+// composite Simpson rule (dv/3 times 1, 4, 2, 4, ..., 4, 1).
+double point_weight(int nv, int quad, int j) {
+    const double dv = grid_dv(nv, quad);
+    if (quad == COSENU_QUAD_TRAPEZOID) return (j == 0 || j == nv - 1) ? 0.5 * dv : dv;
+    if (quad == COSENU_QUAD_SIMPSON) return (j == 0 || j == nv - 1) ? dv / 3.0 : (j % 2 ? 4.0 : 2.0) * dv / 3.0;
+    return dv;
+}
+
+// Unnormalised g(v) ~ exp(-(v-1)^2 / 2 sigma^2) (Sec. 5).
+double gaussian_raw(double v, double sigma) { return std::exp(-(v - 1.0) * (v - 1.0) / (2.0 * sigma * sigma)); }
+
+// sum_j w_j exp(-(v_j-1)^2 / 2 sigma^2), summed in j order: g is divided by it
+// so that sum_j w_j g_j = 1.
+double gaussian_norm(int nv, int quad, double sigma) {
+    double s = 0.0;
+    for (int j = 0; j < nv; ++j) s += gaussian_raw(point_velocity(nv, quad, j), sigma) * point_weight(nv, quad, j);
+    return s;
+}
+
 std::vector<double> bin_velocities(int nv, int quad) {
     std::vector<double> v(nv);
-    const double dv = grid_dv(nv, quad);
-    const double first = quad == COSENU_QUAD_MIDPOINT ? 0.5 : 0.0;
-    for (int j = 0; j < nv; ++j) v[j] = -1.0 + (j + first) * dv;
+    for (int j = 0; j < nv; ++j) v[j] = point_velocity(nv, quad, j);
     return v;
 }
 
-// Quadrature weights of the velocity integral (Sec. 3 and 3.1): dv per bin
-// (Riemann sum), the composite trapezoid rule (ends halved) or the composite
-// Simpson rule (dv/3 times 1, 4, 2, 4, ..., 4, 1).
 std::vector<double> quadrature_weights(int nv, int quad) {
-    const double dv = grid_dv(nv, quad);
-    std::vector<double> w(nv, dv);
-    if (quad == COSENU_QUAD_TRAPEZOID) {
-        w[0] = w[nv - 1] = 0.5 * dv;
-    } else if (quad == COSENU_QUAD_SIMPSON) {
-        for (int j = 0; j < nv; ++j) w[j] = (j == 0 || j == nv - 1) ? dv / 3.0 : (j % 2 ? 4.0 : 2.0) * dv / 3.0;
-    }
+    std::vector<double> w(nv);
+    for (int j = 0; j < nv; ++j) w[j] = point_weight(nv, quad, j);
     return w;
 }
 
 // g(v) ~ exp(-(v-1)^2 / 2 sigma^2) with sum_j w_j g_j = 1 (Sec. 5).
 std::vector<double> gaussian_distribution(int nv, int quad, double sigma) {
-    const std::vector<double> v = bin_velocities(nv, quad), w = quadrature_weights(nv, quad);
+    const double s = gaussian_norm(nv, quad, sigma);
     std::vector<double> g(nv);
-    double s = 0.0;
-    for (int j = 0; j < nv; ++j) {
-        g[j] = std::exp(-(v[j] - 1.0) * (v[j] - 1.0) / (2.0 * sigma * sigma));
-        s += g[j] * w[j];
-    }
-    for (int j = 0; j < nv; ++j) g[j] /= s;
+    for (int j = 0; j < nv; ++j) g[j] = gaussian_raw(point_velocity(nv, quad, j), sigma) / s;
     return g;
 }
 
-// Per-point constants as the kernels read them, [4][nv]: v_j, then g_j, gbar_j
-// and alpha gbar_j, each times w_j / dv.  The kernels form every velocity
-// integral as dv times a plain sum over the grid, so the rule's weights
-// travel inside the distributions (a factor of exactly one for the bins).
-std::vector<double> bin_constants(const cosenu_params &p) {
+// Element k of the per-point constants as the kernels read them, [4][nv]: v_j,
+// then g_j, gbar_j and alpha gbar_j, each times w_j / dv (s_nu, s_nubar: the
+// normalisation sums of gaussian_norm).  The kernels form every velocity
+// integral as dv times a plain sum over the grid, so the rule's weights travel
+// inside the distributions (a factor of exactly one for the bins).  Allocates
+// nothing, so the non-allocating entry point computes the same table.
+double bin_constant_at(const cosenu_params &p, int k, double s_nu, double s_nubar) {
     const int nv = p.nv, quad = p.quadrature;
-    const std::vector<double> v = bin_velocities(nv, quad), w = quadrature_weights(nv, quad);
-    const std::vector<double> g = gaussian_distribution(nv, quad, p.sigma_nu);
-    const std::vector<double> gb = gaussian_distribution(nv, quad, p.sigma_nubar);
-    const double dv = grid_dv(nv, quad);
-    std::vector<double> c(4 * (size_t)nv);
-    for (int j = 0; j < nv; ++j) {
-        const double f = quad == COSENU_QUAD_MIDPOINT ? 1.0 : w[j] / dv;
-        c[j] = v[j];
-        c[nv + j] = g[j] * f;
-        c[2 * nv + j] = gb[j] * f;
-        c[3 * nv + j] = p.alpha * (gb[j] * f);
-    }
+    const int q = k / nv, j = k % nv;
+    const double v = point_velocity(nv, quad, j);
+    if (q == 0) return v;
+    const double f = quad == COSENU_QUAD_MIDPOINT ? 1.0 : point_weight(nv, quad, j) / grid_dv(nv, quad);
+    if (q == 1) return (gaussian_raw(v, p.sigma_nu) / s_nu) * f;
+    const double gb = gaussian_raw(v, p.sigma_nubar) / s_nubar;
+    return q == 2 ? gb * f : p.alpha * (gb * f);
+}
+
+std::vector<double> bin_constants(const cosenu_params &p) {
+    const double s_nu = gaussian_norm(p.nv, p.quadrature, p.sigma_nu);
+    const double s_nubar = gaussian_norm(p.nv, p.quadrature, p.sigma_nubar);
+    std::vector<double> c(4 * (size_t)p.nv);
+    for (size_t k = 0; k < c.size(); ++k) c[k] = bin_constant_at(p, (int)k, s_nu, s_nubar);
     return c;
 }
 

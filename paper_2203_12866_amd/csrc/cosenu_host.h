@@ -15,6 +15,11 @@ const char *strerror_code(int code);
 std::string validate_params(const cosenu_params &p);
 const char *params_problem(const cosenu_params &p, char *buf, size_t nbuf);
 double grid_dv(int nv, int quad);
+double point_velocity(int nv, int quad, int j);
+double point_weight(int nv, int quad, int j);
+double gaussian_raw(double v, double sigma);
+double gaussian_norm(int nv, int quad, double sigma);
+double bin_constant_at(const cosenu_params &p, int k, double s_nu, double s_nubar);
 std::vector<double> bin_velocities(int nv, int quad);
 std::vector<double> quadrature_weights(int nv, int quad);
 std::vector<double> gaussian_distribution(int nv, int quad, double sigma);

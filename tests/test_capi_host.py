@@ -141,3 +141,24 @@ def test_failure_injection_arguments():
     p.nz = 2
     h = ctypes.c_void_p()
     assert L.cosenu_create(ctypes.byref(p), ctypes.byref(h)) == cosenu.EINVAL
+
+
+def test_noalloc_refuses_before_touching_a_device():
+    """cosenu_step_noalloc checks its arguments and the scratch it would need
+    before any HIP call: invalid parameters, a null state, a negative step
+    count and a problem larger than the static scratch array give EINVAL."""
+    lib = cosenu.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below is refused first
+    p = cosenu.default_params()
+    assert lib.cosenu_step_noalloc(None, fake, 1, None) == cosenu.EINVAL
+    assert lib.cosenu_step_noalloc(ctypes.byref(p), None, 1, None) == cosenu.EINVAL
+    assert lib.cosenu_step_noalloc(ctypes.byref(p), fake, -1, None) == cosenu.EINVAL
+    bad = cosenu.default_params()
+    bad.nz = 4
+    assert lib.cosenu_step_noalloc(ctypes.byref(bad), fake, 1, None) == cosenu.EINVAL
+    big = cosenu.default_params()
+    big.nz, big.nv = 4096, 128  # about 100 MB of scratch, above the 64 MiB array
+    assert lib.cosenu_step_noalloc(ctypes.byref(big), fake, 1, None) == cosenu.EINVAL
+    fits = cosenu.default_params()
+    fits.nz, fits.nv = 2048, 128
+    assert lib.cosenu_step_noalloc(ctypes.byref(fits), fake, 0, None) == cosenu.OK  # zero steps: nothing to do
