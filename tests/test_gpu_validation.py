@@ -16,13 +16,16 @@ the equations decouple into advection (Sec. 4.1) and vacuum oscillation
   at long wavelengths and lose power at short ones, FD more (its KO term).
 * Vacuum oscillation of a Gaussian packet (eq:vac_sols) and the minimum of the
   survival probability printed in Sec. 4.2.
-* The CFL study of Sec. 5 (Fig. collosc_dP_varying_Nz): at fixed Nz, delta P
-  at a fixed time does not depend on C for FD + KO (spatial error dominates)
-  but falls with C for WENO7; doubling Nz improves both.
+* The CFL study of Sec. 5 (Fig. collosc_dP_varying_Nz): at fixed Nz,
+  delta P_max and <delta P> at a fixed time do not depend on C for FD + KO
+  (spatial error dominates) but fall with C for WENO7; doubling Nz improves
+  both; the deviation of M0_3 stays at rounding level.
 * The fixed-time-step study of Sec. 5 (eq:kappa, Appendix C) on the
   collective-oscillation setup: with dt fixed and Nz doubling, delta P_max
   falls at the spatial order for FD + KO (kappa ~ 3) and at about 7 for WENO7
-  until the time-integration error takes over and kappa drops to ~0.
+  until the time-integration error takes over and kappa drops to ~0; Appendix
+  C's estimator alpha, from three errors at the same dt, recovers the spatial
+  order where kappa has already dropped.
 * The effect of Kreiss-Oliger dissipation on a box profile (Appendix B):
   without it the Fourier amplitudes stay those of the exact solution while
   the phases are kept only at long wavelengths, which leaves dispersive
@@ -194,6 +197,13 @@ def test_kreiss_oliger_effect_on_box_profile(precision):
     assert np.abs(res[0.0] - exact).sum() > 2 * np.abs(res[0.1] - exact).sum()
 
 
+def _log2_or_nan(x):
+    """log2 of a ratio of error differences; once both errors of a difference
+    sit at the saturated time-integration error the ratio can turn negative
+    (it carries no order there)."""
+    return math.log2(x) if x > 0 else float("nan")
+
+
 def test_fixed_dt_convergence_kappa():
     """delta P_max after 1000 steps at a fixed dt (C = 1 at Nz = 32768), Nz
     doubling from 1024; kappa = log2 of successive ratios (eq:kappa)."""
@@ -201,7 +211,7 @@ def test_fixed_dt_convergence_kappa():
     vmax = 1.0 - 1.0 / nv
     dt = (L / 32768) / vmax
     nzs = [1024, 2048, 4096, 8192, 16384, 32768]
-    kappa = {}
+    kappa, alpha = {}, {}
     for scheme in (wl.FD_KO, wl.FV_WENO7):
         dps = []
         for nz in nzs:
@@ -212,35 +222,58 @@ def test_fixed_dt_convergence_kappa():
                 s.step(steps)
                 dps.append(s.conserved()["dP_max"])
         kappa[scheme] = [math.log2(dps[i] / dps[i + 1]) for i in range(len(dps) - 1)]
-        print(f"scheme {scheme}: dP_max {['%.2e' % x for x in dps]}, kappa {['%.2f' % k for k in kappa[scheme]]}")
+        # Appendix C's estimator of the spatial order from three errors at the
+        # same dt, dz halving (r = 2): the constant time-integration error
+        # cancels in the differences
+        alpha[scheme] = [_log2_or_nan((dps[i] - dps[i + 1]) / (dps[i + 1] - dps[i + 2])) for i in range(len(dps) - 2)]
+        print(f"scheme {scheme}: dP_max {['%.2e' % x for x in dps]}, kappa {['%.2f' % k for k in kappa[scheme]]}, "
+              f"alpha {['%.2f' % k for k in alpha[scheme]]}")
     # FD + KO: spatial error dominates at every Nz, kappa ~ its order 3
     assert all(2.5 < k < 4.2 for k in kappa[wl.FD_KO]), kappa
     assert abs(kappa[wl.FD_KO][-1] - 3.0) < 0.3
     # WENO7: about 7 while the spatial error dominates, then ~0 once the RK4 error at this dt takes over
     assert kappa[wl.FV_WENO7][0] > 6.0 and kappa[wl.FV_WENO7][1] > 6.0, kappa
     assert all(abs(k) < 0.5 for k in kappa[wl.FV_WENO7][-2:]), kappa
+    # alpha: the FD + KO order at every triple; WENO7's order 7 also from the
+    # triple (2048, 4096, 8192), where kappa has already dropped to ~4 because
+    # the time error is no longer negligible at 8192 (beyond that the
+    # differences are at the level of the saturated error and carry no order)
+    assert all(2.5 < a < 4.2 for a in alpha[wl.FD_KO]), alpha
+    assert all(6.0 < a < 8.0 for a in alpha[wl.FV_WENO7][:2]), alpha
+    assert kappa[wl.FV_WENO7][2] < alpha[wl.FV_WENO7][1] - 1.5, (kappa, alpha)
 
 
 def test_error_versus_cfl_and_resolution():
     nv, L, T = 100, 1200.0, 40.0
     cfls = (0.8, 0.4, 0.2)
-    res = {}
+    res, mean, dm3 = {}, {}, {}
     for scheme in (wl.FD_KO, wl.FV_WENO7):
         for nz in (4096, 8192):
             for cfl in cfls:
                 w = dict(wl.small_fd(1), nz=nz, nv=nv, L=L, cfl=cfl, pert_amp=1e-2, phase=0.0, alpha=0.9,
                          scheme=scheme)
                 with cosenu.Sim(w) as s:
+                    c0 = s.conserved()
                     s.step(int(round(T / s.info()["dt"])))
-                    res[scheme, nz, cfl] = s.conserved()["dP_max"]
-    print({k: "%.2e" % v for k, v in res.items()})
-    for nz in (4096, 8192):
-        fd = [res[wl.FD_KO, nz, c] for c in cfls]
-        assert max(fd) / min(fd) < 1.05, fd                       # FD: C does not matter
-        assert res[wl.FV_WENO7, nz, 0.8] > 5 * res[wl.FV_WENO7, nz, 0.2]  # WENO7: smaller steps help
-    for scheme in (wl.FD_KO, wl.FV_WENO7):
-        for c in cfls:
-            assert res[scheme, 8192, c] < 0.5 * res[scheme, 4096, c]  # doubling Nz helps both
+                    c1 = s.conserved()
+                    res[scheme, nz, cfl] = c1["dP_max"]
+                    mean[scheme, nz, cfl] = c1["dP_mean"]
+                    dm3[scheme, nz, cfl] = abs(c1["M0"][3] - c0["M0"][3]) / abs(c0["M0"][3])
+    print("dP_max", {k: "%.2e" % v for k, v in res.items()})
+    print("<dP>", {k: "%.2e" % v for k, v in mean.items()})
+    print("dM0_3 / M0_3", {k: "%.1e" % v for k, v in dm3.items()})
+    # panels (a) and (b): delta P_max and <delta P> follow the same pattern
+    for q in (res, mean):
+        for nz in (4096, 8192):
+            fd = [q[wl.FD_KO, nz, c] for c in cfls]
+            assert max(fd) / min(fd) < 1.05, fd                       # FD: C does not matter
+            assert q[wl.FV_WENO7, nz, 0.8] > 5 * q[wl.FV_WENO7, nz, 0.2]  # WENO7: smaller steps help
+        for scheme in (wl.FD_KO, wl.FV_WENO7):
+            for c in cfls:
+                assert q[scheme, 8192, c] < 0.5 * q[scheme, 4096, c]  # doubling Nz helps both
+    # panel (c): the lepton number M0_3 is conserved by the discrete scheme
+    # (omega = lambda = 0), so its deviation is rounding only, at every C and Nz
+    assert max(dm3.values()) < 1e-12, dm3
 
 
 def _advect_profile(prof, nz, scheme, T=600.0, L=1600.0):
