@@ -8,9 +8,10 @@ bandwidth those updates imply.  The default (headline) workload is the
 largest single-GPU configuration: WENO7 on 2^20 x 512 cells (L = 1e5,
 omega = 1e-3, lambda = 10, ELN-crossing Gaussian family), in the
 FP32-with-FP64-accumulation form, with its FP64 twin beside it.  The same line
-carries, as secondary entries, WENO7 on 65536 x 256 in both forms and the
-batch of 64 uneven instances, each with its roofline, and a copy-bandwidth
-ceiling measured in the same run.
+carries, as secondary entries, WENO7 on 65536 x 256 and FD + KO on
+16384 x 128 (autotuned over single stages, fused stage pairs and the whole
+step in one launch) in both forms and the batch of 64 uneven instances, each
+with its roofline, and a copy-bandwidth ceiling measured in the same run.
 
 Output: one JSON line on stdout.  Inputs are resident in HBM before the
 timed region starts.  --gpus N with N > 1 exits: the library runs on one GPU.
@@ -312,11 +313,16 @@ def batch_main(args, cosenu, torch):
     print(json.dumps(out), flush=True)
 
 
-def kernel_name(w, pairs, form):
+def kernel_name(w, launches, form):
     f = "FP32acc" if form == "fp32acc" else "FP64"
-    if pairs:
+    if launches == 1:
+        return f"quad_kernel<FD,{f}> (the whole RK4 step in one launch)"
+    if launches == 2:
         return f"pair_kernel<FD,{f}> (stages 1+2 and 3+4 fused)"
     return f"stage_kernel<FD,{f}>" if w["scheme"] == 0 else f"stage_kernel<WENO7,{f}>"
+
+
+PATHS = {1: "whole step", 2: "fused stage pairs", 4: "single stages"}
 
 
 def run_workload(cosenu, torch, name, steps, warmup, seg, stage_steps, fused):
@@ -334,14 +340,15 @@ def run_workload(cosenu, torch, name, steps, warmup, seg, stage_steps, fused):
     cells = w["nz"] * w["nv"]
     forms = {}
     for form, r in res.items():
-        pairs = r["launches"] == 2
+        nl = r["launches"]
+        suffix = {1: "/whole", 2: "/pairs", 4: ""}[nl]
         forms[form] = {
             "value": r["updates"], "ms_per_step": r["wall"] * 1e3 / steps, "modelled_gbps": r["gbps_model"],
             "bytes_per_update": r["info"]["bytes_per_step"] / (cells * 4.0),
             "roofline": {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                          "frac": r["achieved_gbps"] / PEAK_HBM_GBPS,
-                         "traffic": measured_traffic(name, form + ("/pairs" if pairs else "")),
-                         "kernel": kernel_name(w, pairs, form), "launches_per_step": r["launches"],
+                         "traffic": measured_traffic(name, form + suffix),
+                         "kernel": kernel_name(w, nl, form), "launches_per_step": nl, "path": PATHS[nl],
                          "avg_launch_us": r["launch_s"] * 1e6, "launch_us_eager": r["stage_us"]},
             "seg_rows": r["seg"],
         }
@@ -374,6 +381,9 @@ def main():
                     help="skip the secondary workloads (WENO7 65536x256 and the 64-instance batch)")
     ap.add_argument("--secondary-steps", type=int, default=200, help="timed steps of the secondary workloads")
     ap.add_argument("--no-fusion", action="store_true", help="four single-stage launches per step")
+    ap.add_argument("--fusion", type=int, default=1, choices=(0, 1, 2),
+                    help="0 single stages, 1 fused (the autotuner picks the path), 2 the whole step in one launch "
+                         "where supported (with --seg-rows, which skips the autotuner)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB between device buffers six times (the reference for the HBM counters)")
@@ -402,8 +412,9 @@ def main():
         return batch_main(args, cosenu, torch)
     ceiling = copy_ceiling(torch)
     print(f"[bench] copy ceiling {ceiling['gbps']:.0f} GB/s", file=sys.stderr, flush=True)
+    fusion = 0 if args.no_fusion else args.fusion
     main_run = run_workload(cosenu, torch, args.workload, args.steps, args.warmup, args.seg_rows, args.stage_steps,
-                            not args.no_fusion)
+                            fusion)
     res = main_run.pop("_res")
     head = res["fp32acc"]
     hf = main_run["forms"]["fp32acc"]
@@ -434,7 +445,7 @@ def main():
         "fp32_vs_fp64_after_run": main_run["fp32_vs_fp64_after_run"],
         "tracked": main_run["tracked"],
     }
-    if res["fp32acc"]["launches"] == 2:  # the same form on four single-stage launches, for comparison
+    if res["fp32acc"]["launches"] < 4:  # the same form on four single-stage launches, for comparison
         single = run_form(cosenu, torch, WORKLOADS[args.workload](1), args.steps, args.warmup, args.seg_rows,
                           args.stage_steps, fused=False)
         print(f"[bench] {args.workload} fp32acc single stages: {single['updates']:.4e} upd/s", file=sys.stderr,
@@ -448,10 +459,10 @@ def main():
     del res, head
     if not args.no_secondary and args.workload == DEFAULT_WORKLOAD:
         sec = {}
-        name = "fv_weno7_65536x256"
-        r3 = run_workload(cosenu, torch, name, args.secondary_steps, args.warmup, None, args.stage_steps, True)
-        r3.pop("_res")
-        sec[name] = r3
+        for name in ("fv_weno7_65536x256", "fd_ko_16384x128"):
+            r3 = run_workload(cosenu, torch, name, args.secondary_steps, args.warmup, None, args.stage_steps, True)
+            r3.pop("_res")
+            sec[name] = r3
         from paper_2203_12866_amd import workloads as wl
         insts = wl.batch_64(4)
         rb = run_batch(cosenu, torch, insts, args.secondary_steps, args.warmup)

@@ -149,6 +149,7 @@ typedef struct {
     int32_t blocks_per_stage;/* workgroups of one stage (or fused pair) launch */
     double bytes_per_step;   /* algorithmic HBM bytes of one RK4 step          */
     int32_t launches_per_step; /* 4 single stages, or 2 fused stage pairs      */
+    int32_t waves_per_workgroup; /* of the single-stage launches (1, 2 or 4)  */
 } cosenu_info_t;
 
 /* Fills *p with the paper's fiducial values (Sec. 5): nz = 512, nv = 32,
@@ -208,14 +209,21 @@ int cosenu_set_stream(cosenu_sim *s, void *hip_stream);
  * Results do not depend on it (bitwise). */
 int cosenu_set_seg_rows(cosenu_sim *s, int32_t seg_rows);
 
-/* Stage fusion (on = 1, the default; 0 = off).  With FD + KO and
- * 32 < nv <= 256 an RK4 step then runs as two fused launches, stages 1 + 2 and
- * stages 3 + 4: the intermediate stage values Y2 and Y4 stay on chip and the
- * moments of the intermediate stage are exchanged between the waves of a
- * workgroup, which cuts the algorithmic bytes per step from 768 to 448 (FP64)
- * or from 704 to 384 (FP32 form).  Other shapes and schemes run four single
- * stages either way.  Results are bitwise those of four single stages.
- * Synchronises the handle's stream; cosenu_info reports launches_per_step. */
+/* Stage fusion (method of lines with classic RK4, Sec. 3.1): on = 0 runs four
+ * single-stage launches per step; on = 1 (the default) fuses stages where the
+ * shape allows it (FD + KO with ko_order <= 2 and 32 < nv <= 256): two
+ * launches per step, stages 1 + 2 and 3 + 4, the intermediate stage values Y2
+ * and Y4 on chip and their moments exchanged between the waves of a
+ * workgroup, 448 (FP64) or 384 (FP32 form) algorithmic bytes per cell and step
+ * against 768 or 704 for single stages; after cosenu_autotune, on = 1 takes the
+ * fastest path it measured.  on = 2 runs the whole RK4 step in one launch
+ * where the shape allows it (also nz >= 16): the four stages march each
+ * segment together with Y2, Y3, Y4 and acc on chip, 128 bytes per cell and
+ * step in both forms (the state read and written once).  Other shapes and
+ * schemes fall back to what they support.  Results are bitwise those of four
+ * single stages on every path.  Other values of on: COSENU_EINVAL.
+ * Synchronises the handle's stream; cosenu_info reports launches_per_step
+ * (4, 2 or 1). */
 int cosenu_set_fusion(cosenu_sim *s, int32_t on);
 
 /* Times nsteps steps on the handle's stream with HIP events (after the work
@@ -227,11 +235,19 @@ int cosenu_time_steps(cosenu_sim *s, int64_t nsteps, double *ms);
  * zeros.  Synchronises. */
 int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage);
 
-/* Picks seg_rows by timing candidate launch shapes (single stages 1-3, or
- * both fused pairs) on the handle's buffers; the state, its moments and all
- * later results are unchanged.  Results are cached per (kernel variant,
- * precision, nv, nz bucket) and path (fused or not) for the process.
- * *seg_rows receives the choice (may be NULL).  Synchronises. */
+/* Picks the launch shape by timing whole RK4 steps on the handle's buffers:
+ * the segment length of the fused stage pairs (where the shape allows them and
+ * fusion is on), the segment length and the waves per workgroup (1, 2 or 4) of
+ * the single stages, and the faster of the two paths (fused pairs recompute a
+ * two-row halo of the intermediate stage on chip; single stages re-read their
+ * stencil halo from the caches).  The state, its moments and all later results
+ * are unchanged (results do not depend on launch shapes).  The choice is
+ * cached per device and (kernel variant, precision, nv, nz bucket) for the
+ * process, and handles created later start from it; if the environment
+ * variable COSENU_TUNE_CACHE names a file, the cache is also read from that
+ * file on first use and written back after every tuning (so later processes
+ * start tuned).  cosenu_set_fusion afterwards overrides the path.
+ * *seg_rows receives the segment length (may be NULL).  Synchronises. */
 int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows);
 
 const char *cosenu_strerror(int code);
@@ -242,8 +258,8 @@ const char *cosenu_last_error(const cosenu_sim *s);
  * code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc.  It advances a state the caller owns on the device by nsteps RK4
  * steps, exactly as cosenu_step advances a handle created from *p (same
- * kernels, same launch shapes: fused stage pairs where the shape allows them;
- * same arithmetic, so the same results bit for bit).  Every intermediate
+ * kernels: fused stage pairs where the shape allows them; default launch
+ * shapes; same arithmetic, so the same results bit for bit).  Every intermediate
  * buffer (stage values, the accumulator, the angular-moment partials of
  * each stage input, the per-point constants) lives in one static device
  * array of COSENU_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from

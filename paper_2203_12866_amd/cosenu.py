@@ -74,7 +74,7 @@ class Info(ctypes.Structure):
         ("step", ctypes.c_int64), ("device_bytes", ctypes.c_size_t),
         ("seg_rows", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("v_chunks", ctypes.c_int32),
         ("blocks_per_stage", ctypes.c_int32), ("bytes_per_step", ctypes.c_double),
-        ("launches_per_step", ctypes.c_int32),
+        ("launches_per_step", ctypes.c_int32), ("waves_per_workgroup", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -278,9 +278,11 @@ class Sim:
         self._check(_lib().cosenu_time_stages(self._h, int(n), ms), "cosenu_time_stages")
         return list(ms)
 
-    def set_fusion(self, on: bool):
-        """Fused stage pairs where supported (default on); results are bitwise the same."""
-        self._check(_lib().cosenu_set_fusion(self._h, 1 if on else 0), "cosenu_set_fusion")
+    def set_fusion(self, on):
+        """0 / False: four single stages; 1 / True: fused (stage pairs, or the
+        path the autotuner chose); 2: the whole RK4 step in one launch where the
+        shape allows it.  Results are bitwise the same on every path."""
+        self._check(_lib().cosenu_set_fusion(self._h, int(on)), "cosenu_set_fusion")
 
     def autotune(self) -> int:
         seg = ctypes.c_int32()

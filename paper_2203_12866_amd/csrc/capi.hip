@@ -12,6 +12,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <unistd.h>
 #include <vector>
 
 #include "cosenu.h"
@@ -254,6 +255,11 @@ double bytes_per_cell_step(int form) {
     return form == COSENU_FP64 ? 12.0 * 64.0 : 10.0 * 64.0 + 2.0 * 32.0;
 }
 
+double bytes_per_cell_step_whole(int) {
+    // one launch per step reads the state and writes the new state, FP64 in both forms
+    return 2.0 * 64.0;
+}
+
 double bytes_per_cell_step_fused(int form) {
     // pair 0 reads y, writes Y3 and acc; pair 1 reads Y3, y and acc, writes y
     return form == COSENU_FP64 ? 7.0 * 64.0 : 5.0 * 64.0 + 2.0 * 32.0;
@@ -291,6 +297,7 @@ void fill_desc_constants(const cosenu_params &p, InstDesc &d) {
     }
     d.weno_eps = p.weno_eps;
     d.ps = (size_t)p.nz * p.nv + kPlanePad;
+    d.wpb = kWavesPerBlock;
     set_shape(d, default_seg_rows(p.nz, p.nv));
 }
 
@@ -322,23 +329,109 @@ void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vect
     out->nonfinite = (int64_t)a[11];
 }
 
-// Launch-shape cache shared by single instances and batches.
+// Launch-shape cache shared by single instances, batches and the
+// non-allocating entry point: per device and (kernel variant, form, nv,
+// nz bucket), the tuned shapes of both paths and the faster path.  With
+// COSENU_TUNE_CACHE naming a file, entries are read from it on first use and
+// the whole cache is written back (to a temporary file, then renamed) after
+// every tuning, so that later processes on the same kind of device start tuned.
+namespace {
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, bool>, int> g_tune_cache;
+bool g_tune_loaded = false;
+std::map<std::string, TuneEntry> g_tune_cache;  // key: "device scheme form nv bucket"
 
-int tuned_seg(int scheme, int form, int nz, int nv, bool pairs) {
+int nz_bucket(int nz) {
     int bucket = 0;
     while ((1 << (bucket + 1)) <= nz) ++bucket;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_cache.find(std::make_tuple(scheme, form, nv, bucket, pairs));
-    return it == g_tune_cache.end() ? 0 : it->second;
+    return bucket;
 }
 
-void store_tuned_seg(int scheme, int form, int nz, int nv, bool pairs, int seg) {
-    int bucket = 0;
-    while ((1 << (bucket + 1)) <= nz) ++bucket;
+// The current device's architecture and compute-unit count: shapes tuned on
+// one kind of GPU are not reused on another.
+std::string device_tag() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return arch + "/" + std::to_string(prop.multiProcessorCount);
+}
+
+std::string tune_key(int scheme, int form, int nz, int nv) {
+    return device_tag() + " " + std::to_string(scheme) + " " + std::to_string(form) + " " + std::to_string(nv) + " " +
+           std::to_string(nz_bucket(nz));
+}
+
+const char *tune_file() {
+    const char *f = std::getenv("COSENU_TUNE_CACHE");
+    return f && *f ? f : nullptr;
+}
+
+// One line per entry: device scheme form nv bucket seg_pairs seg_quad seg_single wpb path.
+void load_tune_file_locked() {
+    g_tune_loaded = true;
+    const char *path = tune_file();
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char dev[128];
+    int scheme, form, nv, bucket, sp, sq, ss, wpb, pth;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        if (std::sscanf(line, "%127s %d %d %d %d %d %d %d %d %d", dev, &scheme, &form, &nv, &bucket, &sp, &sq, &ss,
+                        &wpb, &pth) != 10)
+            continue;
+        if (sp < 0 || sq < 0 || ss < 0 || (wpb != 0 && wpb != 1 && wpb != 2 && wpb != 4) || pth < -1 || pth > 2)
+            continue;
+        TuneEntry e;
+        e.seg_pairs = sp;
+        e.seg_quad = sq;
+        e.seg_single = ss;
+        e.wpb = wpb;
+        e.path = pth;
+        g_tune_cache[std::string(dev) + " " + std::to_string(scheme) + " " + std::to_string(form) + " " +
+                     std::to_string(nv) + " " + std::to_string(bucket)] = e;
+    }
+    std::fclose(f);
+}
+
+void save_tune_file_locked() {
+    const char *path = tune_file();
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "# cosenu launch-shape cache: device scheme form nv nz_bucket seg_pairs seg_whole_step "
+                    "seg_single waves_per_workgroup path(0 single stages, 1 fused pairs, 2 whole step, -1 unknown)\n");
+    for (const auto &kv : g_tune_cache)
+        std::fprintf(f, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.seg_pairs, kv.second.seg_quad,
+                     kv.second.seg_single, kv.second.wpb, kv.second.path);
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
+}
+}  // namespace
+
+TuneEntry tuned_entry(int scheme, int form, int nz, int nv) {
+    const std::string key = tune_key(scheme, form, nz, nv);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[std::make_tuple(scheme, form, nv, bucket, pairs)] = seg;
+    if (!g_tune_loaded) load_tune_file_locked();
+    auto it = g_tune_cache.find(key);
+    return it == g_tune_cache.end() ? TuneEntry() : it->second;
+}
+
+void store_tuned_entry(int scheme, int form, int nz, int nv, const TuneEntry &e) {
+    const std::string key = tune_key(scheme, form, nz, nv);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) load_tune_file_locked();
+    g_tune_cache[key] = e;
+    save_tune_file_locked();
+}
+
+int tuned_seg(int scheme, int form, int nz, int nv, bool pairs) {
+    const TuneEntry e = tuned_entry(scheme, form, nz, nv);
+    return pairs ? e.seg_pairs : e.seg_single;
 }
 
 }  // namespace cosenu
@@ -353,11 +446,14 @@ struct cosenu_sim {
     // step graphs for a state held in buffer 0 or 1 (g1: one step, gN: gN_steps)
     hipGraphExec_t g1[2] = {nullptr, nullptr}, gN[2] = {nullptr, nullptr};
     int gN_steps = 16;
-    // The fused pairs write the new state into the other of two buffers (the
-    // second fused pair still reads the old state on the halo rows of its
-    // segments, which neighbouring workgroups are rewriting); d.y is the buffer
-    // holding the current state, d.ya the other one.
+    // The fused paths write the new state into the other of two buffers (a
+    // fused launch still reads the old state on the halo rows of its segments,
+    // which neighbouring workgroups are rewriting); d.y is the buffer holding
+    // the current state, d.ya the other one.  The whole-step path also
+    // alternates the moment partials of the state between mom_buf[0] and
+    // mom_buf[1] (the other paths keep them in mom_buf[0]).
     double *state_buf[2] = {nullptr, nullptr};
+    double *mom_buf[4] = {nullptr, nullptr, nullptr, nullptr};
     int parity = 0;
     bool graphs_ok = false;
     double t = 0.0;
@@ -368,24 +464,52 @@ struct cosenu_sim {
     double *diag_part = nullptr;   // [max tasks][kDiagQ]
     size_t diag_cap = 0;           // in tasks
     double *mom_out = nullptr;     // [nz][vchunks][8]
-    bool fusion_wanted = true;     // run fused stage pairs where the kernels support the shape
+    int fusion = 1;                // cosenu_set_fusion: 0 single stages, 1 fused (default), 2 whole step preferred
+    int tuned_path = -1;           // the autotuner's (or the cache's) faster path: 0, 1 or 2; -1 none
     std::string err;
 };
 
 namespace {
-bool fused(const cosenu_sim *s) { return s->fusion_wanted && pair_supported(s->d); }
-void point_state(InstDesc &d, const cosenu_sim *s, int p) {
+// The path a step takes: 0 four single stages, 1 two fused stage pairs, 2 one
+// whole-step launch.  Fusion off means single stages; otherwise the tuned path
+// (or, untuned, fused pairs, or the whole step when preferred), falling back to
+// what the shape supports.
+int path_of(const cosenu_sim *s, const InstDesc &d) {
+    if (s->fusion == 0) return 0;
+    const int want = s->tuned_path >= 0 ? s->tuned_path : (s->fusion == 2 ? 2 : 1);
+    if (want == 2 && quad_supported(d)) return 2;
+    if (want >= 1 && pair_supported(d)) return 1;
+    return 0;
+}
+int path_of(const cosenu_sim *s) { return path_of(s, s->d); }
+bool fused(const cosenu_sim *s) { return path_of(s) != 0; }
+void point_state(InstDesc &d, const cosenu_sim *s, int p, int path) {
     d.y = s->state_buf[p];
     d.ya = s->state_buf[1 - p];
+    const int m = path == 2 ? p : 0;
+    d.mom[0] = s->mom_buf[m];
+    d.mom[1] = s->mom_buf[1 - m];
 }
 void set_parity(cosenu_sim *s, int p) {
     s->parity = p;
-    point_state(s->d, s, p);
+    point_state(s->d, s, p, path_of(s));
 }
-int launches_per_step(const cosenu_sim *s) { return fused(s) ? 2 : 4; }
-// launch k of a step: a fused stage pair, or one single stage
+int launches_per_step(const cosenu_sim *s) {
+    const int path = path_of(s);
+    return path == 2 ? 1 : path == 1 ? 2 : 4;
+}
+// launch k of a step: the whole step, a fused stage pair, or one single stage
 hipError_t launch_k(const cosenu_sim *s, int k, hipStream_t st) {
-    return fused(s) ? launch_pair(s->d, k, st) : launch_stage(s->d, k, blocks_for(s->d), st);
+    const int path = path_of(s);
+    if (path == 2) return launch_quad(s->d, st);
+    return path == 1 ? launch_pair(s->d, k, st) : launch_stage(s->d, k, blocks_for(s->d), st);
+}
+double bytes_per_step_of(const cosenu_sim *s) {
+    const int path = path_of(s);
+    const double per_cell = path == 2 ? bytes_per_cell_step_whole(s->prm.precision)
+                          : path == 1 ? bytes_per_cell_step_fused(s->prm.precision)
+                                      : bytes_per_cell_step(s->prm.precision);
+    return per_cell * (double)s->d.nz * s->d.nv;
 }
 }  // namespace
 
@@ -422,13 +546,17 @@ void destroy_graphs(cosenu_sim *s) {
 }
 
 // nsteps steps from a state in buffer p: four single stages per step (the
-// state stays in place), or two fused pairs (the state changes buffer)
+// state stays in place), two fused pairs or one whole-step launch (the state
+// changes buffer)
 int enqueue_steps(cosenu_sim *s, hipStream_t st, int nsteps, int p) {
     InstDesc d = s->d;
-    const bool pairs = fused(s);
+    const int path = path_of(s);
     for (int k = 0; k < nsteps; ++k) {
-        point_state(d, s, p);
-        if (pairs) {
+        point_state(d, s, p, path);
+        if (path == 2) {
+            HIPCHK(s, launch_quad(d, st));
+            p ^= 1;
+        } else if (path == 1) {
             HIPCHK(s, launch_pair(d, 0, st));
             HIPCHK(s, launch_pair(d, 1, st));
             p ^= 1;
@@ -588,8 +716,15 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) try {
     s->stream = s->own_stream;
 
     fill_desc_constants(*p, s->d);
-    const int tuned = tuned_seg(s->d.scheme, p->precision, p->nz, p->nv, fused(s));
-    if (tuned > 0) set_shape(s->d, tuned);
+    {
+        // launch shapes from the tuning cache, if this shape was tuned before
+        const TuneEntry e = tuned_entry(s->d.scheme, p->precision, p->nz, p->nv);
+        s->tuned_path = e.path;
+        if (e.wpb > 0) s->d.wpb = e.wpb;
+        const int path = path_of(s);
+        const int tuned = path == 2 ? e.seg_quad : path == 1 ? e.seg_pairs : e.seg_single;
+        if (tuned > 0) set_shape(s->d, tuned);
+    }
 
     const int nz = p->nz, nv = p->nv;
     const size_t f64 = 8 * s->d.ps * sizeof(double);
@@ -602,14 +737,15 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) try {
     s->d.acc = (double *)ptr;
     if ((rc = sim_alloc(s, &ptr, f64))) return fail(rc);
     s->state_buf[1] = (double *)ptr;
-    set_parity(s, 0);
     if ((rc = sim_alloc(s, &ptr, ybbytes))) return fail(rc);
     s->d.yb = ptr;
     const size_t mom_bytes = (size_t)nz * s->d.vchunks * 2 * kMomQ * sizeof(double);
     for (int k = 0; k < 4; ++k) {
         if ((rc = sim_alloc(s, &ptr, mom_bytes))) return fail(rc);
+        s->mom_buf[k] = (double *)ptr;
         s->d.mom[k] = (double *)ptr;
     }
+    set_parity(s, 0);
     // per-bin constants
     const std::vector<double> hostc = bin_constants(*p);
     double *consts = nullptr;
@@ -648,15 +784,15 @@ int cosenu_step(cosenu_sim *s, int64_t nsteps) try {
         int rc = build_graphs(s);
         if (rc) return rc;
     }
-    const bool pairs = fused(s);
+    const bool moves = fused(s);  // the fused paths move the state to the other buffer every step
     int64_t big = nsteps / s->gN_steps, rem = nsteps % s->gN_steps;
     for (int64_t k = 0; k < big; ++k) {
         HIPCHK(s, hipGraphLaunch(s->gN[s->parity], s->stream));
-        if (pairs && (s->gN_steps & 1)) set_parity(s, s->parity ^ 1);
+        if (moves && (s->gN_steps & 1)) set_parity(s, s->parity ^ 1);
     }
     for (int64_t k = 0; k < rem; ++k) {
         HIPCHK(s, hipGraphLaunch(s->g1[s->parity], s->stream));
-        if (pairs) set_parity(s, s->parity ^ 1);
+        if (moves) set_parity(s, s->parity ^ 1);
     }
     s->step += nsteps;
     s->t += (double)nsteps * s->d.dt;
@@ -730,9 +866,9 @@ int cosenu_info(cosenu_sim *s, cosenu_info_t *out) try {
     out->lanes_per_row = 1 << s->d.lr_log2;
     out->v_chunks = s->d.vchunks;
     out->blocks_per_stage = fused(s) ? s->d.nseg : blocks_for(s->d);
-    out->bytes_per_step = (fused(s) ? bytes_per_cell_step_fused(s->prm.precision) : bytes_per_cell_step(s->prm.precision)) *
-                          (double)s->d.nz * s->d.nv;
+    out->bytes_per_step = bytes_per_step_of(s);
     out->launches_per_step = launches_per_step(s);
+    out->waves_per_workgroup = s->d.wpb;
     return COSENU_OK;
 } COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
@@ -749,7 +885,9 @@ int cosenu_set_seg_rows(cosenu_sim *s, int32_t seg_rows) try {
     HIPCHK(s, hipStreamSynchronize(s->stream));
     int seg = seg_rows;
     if (seg == 0) {
-        seg = tuned_seg(s->d.scheme, s->prm.precision, s->prm.nz, s->prm.nv, fused(s));
+        const TuneEntry e = tuned_entry(s->d.scheme, s->prm.precision, s->prm.nz, s->prm.nv);
+        const int path = path_of(s);
+        seg = path == 2 ? e.seg_quad : path == 1 ? e.seg_pairs : e.seg_single;
         if (seg == 0) seg = default_seg_rows(s->prm.nz, s->prm.nv);
     }
     set_shape(s->d, seg);
@@ -758,9 +896,13 @@ int cosenu_set_seg_rows(cosenu_sim *s, int32_t seg_rows) try {
 
 int cosenu_set_fusion(cosenu_sim *s, int32_t on) try {
     SIM_CHECK(s);
-    if (on != 0 && on != 1) return COSENU_EINVAL;
+    if (on < 0 || on > 2) return COSENU_EINVAL;
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    s->fusion_wanted = on != 0;
+    s->fusion = on;
+    s->tuned_path = -1;
+    // the moments of the state may live in another buffer on the new path
+    set_parity(s, s->parity);
+    HIPCHK(s, launch_moments_init(s->d, blocks_for(s->d), s->stream));
     return build_graphs(s);
 } COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
@@ -798,7 +940,7 @@ int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage) try {
             if (!rc && launch_k(s, stage, s->stream) != hipSuccess) rc = COSENU_EDEVICE;
             if (!rc && hipEventRecord(ev[2 * stage + 1], s->stream) != hipSuccess) rc = COSENU_EDEVICE;
         }
-        if (!rc && nl == 2) set_parity(s, s->parity ^ 1);  // the fused pairs moved the state
+        if (!rc && nl <= 2) set_parity(s, s->parity ^ 1);  // the fused paths moved the state
         if (!rc && hipEventSynchronize(ev[2 * nl - 1]) != hipSuccess) rc = COSENU_EDEVICE;
         for (int stage = 0; stage < nl && !rc; ++stage) {
             float f = 0.f;
@@ -819,59 +961,135 @@ int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage) try {
 int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) try {
     SIM_CHECK(s);
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    // Stages 1..3 write only scratch (Y2, Y3, Y4, acc and the moments of
-    // those stage values), so timing them leaves the state untouched.  Both
-    // fused pairs are timed: the second writes the new state into the other
-    // state buffer (scratch until the step is taken) and the moments of that
-    // state over those of the current one, which are rebuilt from the state
-    // afterwards with the producer's own arithmetic.  The tuned length is
-    // cached per (kernel variant, form, nv, nz bucket) and path.
-    // segment lengths about sqrt(2) apart: the workgroup count of the fused pairs
-    // (one per segment) has to land just under a whole number of resident rounds
+    // Every candidate is timed over whole RK4 steps on the handle's buffers,
+    // leaving the state untouched: stages 1-3 write only scratch (Y2, Y3, Y4,
+    // acc and the moments of those stage values); stage 4 is timed with its
+    // output redirected onto acc, which it reads point by point (each value is
+    // read before it is overwritten, by the same lane); the second fused pair
+    // writes the other state buffer, scratch until a step is taken.  Stage 4 and
+    // the fused pairs overwrite the moments of the current state, which are
+    // rebuilt afterwards from the state with the producer's own arithmetic.
+    //
+    // Search: the segment length of the fused pairs (where the shape allows
+    // them and fusion is on), the segment length of the single stages with 4
+    // waves per workgroup, then 1 and 2 waves per workgroup at that length,
+    // then the faster of the two paths.  Segment lengths are about sqrt(2)
+    // apart: the workgroup count of the fused pairs (one per segment) has to
+    // land just under a whole number of resident rounds.
     const int cands[] = {4, 6, 8, 11, 16, 22, 32, 45, 64, 90, 128, 181, 256};
     const InstDesc keep = s->d;
-    int best = keep.seg;
-    double best_ms = 1e300;
+    const bool try_pairs = s->fusion != 0 && pair_supported(s->d);
+    const bool try_quad = s->fusion != 0 && quad_supported(s->d);
     hipEvent_t a, b;
     HIPCHK(s, hipEventCreate(&a));
     HIPCHK(s, hipEventCreate(&b));
-    for (int c : cands) {
-        if (c > s->d.nz) break;
-        set_shape(s->d, c);
-        const int ntime = fused(s) ? 2 : 3;
-        // the fastest of five timed repetitions (after one to warm up), each
-        // three passes over the launches: candidates a few percent apart have
-        // to be told apart through run-to-run jitter
-        double total = 1e300;
-        bool ok = true;
-        for (int rep = 0; rep < 6 && ok; ++rep) {
-            ok = hipEventRecord(a, s->stream) == hipSuccess;
-            for (int pass = 0; pass < 3 && ok; ++pass)
-                for (int stage = 0; stage < ntime && ok; ++stage) ok = launch_k(s, stage, s->stream) == hipSuccess;
-            ok = ok && hipEventRecord(b, s->stream) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
-            float f = 0.f;
-            ok = ok && hipEventElapsedTime(&f, a, b) == hipSuccess;
-            if (rep > 0) total = std::min(total, (double)f);
-        }
-        if (!ok) {
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
             (void)hipEventDestroy(a);
             (void)hipEventDestroy(b);
-            s->d = keep;
-            s->err = "autotune launch failed";
-            return COSENU_EDEVICE;
         }
-        if (total < best_ms) {
-            best_ms = total;
-            best = c;
+    } ev{a, b};
+    // one pass = one RK4 step of the given path (0 single stages, 1 fused
+    // pairs, 2 whole step) and shape
+    auto pass = [&](const InstDesc &d, int path) -> bool {
+        if (path == 2) {
+            // the whole step writes the other state buffer and the other moment buffer
+            InstDesc dq = d;
+            point_state(dq, s, s->parity, 2);
+            return launch_quad(dq, s->stream) == hipSuccess;
+        }
+        if (path == 1) return launch_pair(d, 0, s->stream) == hipSuccess && launch_pair(d, 1, s->stream) == hipSuccess;
+        InstDesc d4 = d;
+        d4.y = d.acc;  // stage 4 writes over acc (scratch) instead of the state
+        const int nb = blocks_for(d);
+        return launch_stage(d, 0, nb, s->stream) == hipSuccess && launch_stage(d, 1, nb, s->stream) == hipSuccess &&
+               launch_stage(d, 2, nb, s->stream) == hipSuccess && launch_stage(d4, 3, nb, s->stream) == hipSuccess;
+    };
+    // milliseconds per step: the fastest of several repetitions (after one to
+    // warm up), so candidates a few percent apart are told apart through
+    // run-to-run jitter; fewer repetitions for long steps
+    auto time_step = [&](const InstDesc &d, int path, double *ms) -> bool {
+        float f = 0.f;
+        if (!(hipEventRecord(a, s->stream) == hipSuccess && pass(d, path) &&
+              hipEventRecord(b, s->stream) == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+              hipEventElapsedTime(&f, a, b) == hipSuccess))
+            return false;
+        const int reps = f > 20.f ? 2 : 5, passes = f > 5.f ? 1 : 3;
+        double best = 1e300;
+        for (int rep = 0; rep < reps; ++rep) {
+            bool ok = hipEventRecord(a, s->stream) == hipSuccess;
+            for (int k = 0; k < passes && ok; ++k) ok = pass(d, path);
+            ok = ok && hipEventRecord(b, s->stream) == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+                 hipEventElapsedTime(&f, a, b) == hipSuccess;
+            if (!ok) return false;
+            best = std::min(best, (double)f / passes);
+        }
+        *ms = best;
+        return true;
+    };
+    auto fail = [&]() {
+        s->d = keep;
+        set_parity(s, s->parity);
+        (void)launch_moments_init(s->d, blocks_for(s->d), s->stream);
+        (void)hipStreamSynchronize(s->stream);
+        s->err = "autotune launch failed";
+        return COSENU_EDEVICE;
+    };
+    // the fastest segment length of one path at the given waves per workgroup
+    auto sweep = [&](int path, int wpb, int *seg_out, double *ms_out) -> bool {
+        *ms_out = 1e300;
+        for (int c : cands) {
+            if (c > keep.nz) break;
+            InstDesc d = keep;
+            d.wpb = wpb;
+            set_shape(d, c);
+            double ms;
+            if (!time_step(d, path, &ms)) return false;
+            if (ms < *ms_out) {
+                *ms_out = ms;
+                *seg_out = c;
+            }
+        }
+        return true;
+    };
+    TuneEntry e = tuned_entry(keep.scheme, s->prm.precision, s->prm.nz, s->prm.nv);
+    double ms_pairs = 1e300, ms_single = 1e300, ms_quad = 1e300;
+    int seg_pairs = keep.seg, seg_single = keep.seg, seg_quad = keep.seg, wpb = kWavesPerBlock;
+    if (try_quad && !sweep(2, kWavesPerBlock, &seg_quad, &ms_quad)) return fail();
+    if (try_pairs && !sweep(1, kWavesPerBlock, &seg_pairs, &ms_pairs)) return fail();
+    if (!sweep(0, kWavesPerBlock, &seg_single, &ms_single)) return fail();
+    for (int w : {2, 1}) {
+        InstDesc d = keep;
+        d.wpb = w;
+        set_shape(d, seg_single);
+        double ms;
+        if (!time_step(d, 0, &ms)) return fail();
+        if (ms < ms_single) {
+            ms_single = ms;
+            wpb = w;
         }
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    int path = 0;
+    double best = ms_single;
+    if (try_pairs && ms_pairs <= best) {
+        path = 1;
+        best = ms_pairs;
+    }
+    if (try_quad && ms_quad <= best) path = 2;
+    e.seg_single = seg_single;
+    e.wpb = wpb;
+    if (try_pairs) e.seg_pairs = seg_pairs;
+    if (try_quad) e.seg_quad = seg_quad;
+    if (try_pairs || try_quad) e.path = path;
     s->d = keep;
-    set_shape(s->d, best);
-    if (fused(s)) HIPCHK(s, launch_moments_init(s->d, blocks_for(s->d), s->stream));
-    store_tuned_seg(s->d.scheme, s->prm.precision, s->prm.nz, s->prm.nv, fused(s), best);
-    if (seg_rows) *seg_rows = best;
+    s->d.wpb = wpb;
+    if (try_pairs || try_quad) s->tuned_path = path;
+    set_shape(s->d, path == 2 ? seg_quad : path == 1 ? seg_pairs : seg_single);
+    set_parity(s, s->parity);  // the moments of the state live where the chosen path keeps them
+    HIPCHK(s, launch_moments_init(s->d, blocks_for(s->d), s->stream));
+    store_tuned_entry(keep.scheme, s->prm.precision, s->prm.nz, s->prm.nv, e);
+    if (seg_rows) *seg_rows = s->d.seg;
     return build_graphs(s);
 } COSENU_ABI_CATCH(s ? &s->err : nullptr)
 

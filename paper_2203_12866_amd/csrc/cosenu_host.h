@@ -30,14 +30,26 @@ int default_seg_rows(int nz, int nv);
 void set_shape(InstDesc &d, int seg);
 double bytes_per_cell_step(int form);
 double bytes_per_cell_step_fused(int form);
+double bytes_per_cell_step_whole(int form);
 void fill_desc_constants(const cosenu_params &p, InstDesc &d);
 hipError_t moments_to_host(const InstDesc &d, double *scratch, hipStream_t st, double *out);
 hipError_t rows_to_host(const InstDesc &d, int64_t z0, int nrows, hipStream_t st, double *out);
 void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vector<double> &part, double ee0n,
                       double ee0b, double t, int64_t step, cosenu_conserved_t *out);
-// tuned segment length per (kernel variant, form, nv, nz bucket) and path (fused stage pairs or single stages); 0 if none
+// Tuned launch shapes per device and (kernel variant, form, nv, nz bucket);
+// zeros where not tuned.  Kept for the process, and in the file named by
+// COSENU_TUNE_CACHE when that is set.
+struct TuneEntry {
+    int seg_pairs = 0;   // fused stage pairs: rows per segment
+    int seg_quad = 0;    // whole step in one launch: rows per segment
+    int seg_single = 0;  // single stages: rows per segment
+    int wpb = 0;         // single stages: waves per workgroup (1, 2 or 4)
+    int path = -1;       // the fastest full step: 0 single stages, 1 fused pairs, 2 whole step, -1 not compared
+};
+TuneEntry tuned_entry(int scheme, int form, int nz, int nv);
+void store_tuned_entry(int scheme, int form, int nz, int nv, const TuneEntry &e);
+// the tuned segment length of one path, 0 if none
 int tuned_seg(int scheme, int form, int nz, int nv, bool pairs);
-void store_tuned_seg(int scheme, int form, int nz, int nv, bool pairs, int seg);
 
 // ---- no C++ exception crosses the C ABI ------------------------------------
 // Every extern "C" entry point returning a code is a function-try-block that

@@ -9,7 +9,8 @@
 namespace cosenu {
 
 constexpr int kWave = 64;           // CDNA wavefront width
-constexpr int kWavesPerBlock = 4;   // stage kernels run 256-thread workgroups
+constexpr int kWavesPerBlock = 4;   // default (and largest) waves per stage workgroup; diagnostics and
+                                    // batch kernels always run 4 (256 threads)
 constexpr int kMomQ = 6;            // reduced quantities per row and part:
                                     //   sum D3, sum ReDex, sum ImDex, and the same times v
 constexpr int kDiagQ = 12;         // per-task partials of the conserved-quantity kernel
@@ -31,6 +32,7 @@ struct InstDesc {
     int32_t nrowtasks; // nseg * vchunks: (segment, chunk) pairs
     int32_t tps;       // stage tasks per species: nrowtasks padded to a multiple of the groups per wave
     int32_t ntasks;    // stage tasks: 2 * tps (neutrinos, then antineutrinos)
+    int32_t wpb;       // waves per workgroup of the single-instance stage and moment kernels: 1, 2 or 4
     double dz_inv;     // 1 / dz
     double dt;
     double mudv;       // mu * dv
@@ -60,6 +62,7 @@ struct WaveTask {
 };
 
 // ---- launchers (stage_kernels.hip) -----------------------------------------
+// single-instance launches run blocks workgroups of d.wpb waves
 hipError_t launch_stage(const InstDesc &d, int stage, int blocks, hipStream_t st);
 hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st);
 // wave_rows: every instance of the task list has nv > 32 (one row group per wave)
@@ -71,6 +74,12 @@ int batch_waves_per_cu(int scheme, int form, bool wave_rows);
 // one workgroup of 2 vchunks waves per segment (d.nseg workgroups)
 bool pair_supported(const InstDesc &d);
 hipError_t launch_pair(const InstDesc &d, int pair, hipStream_t st);
+// a whole RK4 step in one launch (FD + KO, 32 < nv <= 256, nz >= 16): reads the
+// state in d.y and its moment partials in d.mom[0], writes the new state into
+// d.ya and its moment partials into d.mom[1]; one workgroup of 2 vchunks waves
+// per segment (d.nseg workgroups)
+bool quad_supported(const InstDesc &d);
+hipError_t launch_quad(const InstDesc &d, hipStream_t st);
 // batched fused stage pairs: W = 2 vchunks waves per workgroup, one (instance,
 // segment) task per workgroup and turn (WaveTask.task0 = segment)
 hipError_t launch_batch_pair(const InstDesc *d_descs, const WaveTask *d_tasks, int ntasks, int form, int pair, int W,
@@ -87,7 +96,8 @@ hipError_t launch_init_state(const InstDesc &d, double L, double amp, double wid
 // per row and chunk [nz][vchunks][8]: dv sum D_q and dv sum v D_q, q = ee, xx, Re ex, Im ex
 hipError_t launch_moments_out(const InstDesc &d, double *out, int blocks, hipStream_t st);
 
-// number of workgroups covering all stage tasks / all (segment, chunk) tasks
+// number of workgroups covering all stage tasks (d.wpb waves each) / all
+// (segment, chunk) tasks (kWavesPerBlock waves each)
 int blocks_for(const InstDesc &d);
 int row_blocks_for(const InstDesc &d);
 int groups_per_wave(const InstDesc &d);

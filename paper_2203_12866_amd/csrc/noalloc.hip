@@ -1,8 +1,9 @@
 // cosenu_step_noalloc: RK4 steps of a caller-owned device state with every
 // intermediate buffer in one static device array, for callers that cannot
 // allocate device memory.  It runs the kernels cosenu_step runs (fused stage
-// pairs where the shape allows them, else four single stages per step), so its
-// results are those of a handle created from the same parameters.
+// pairs where the shape allows them, else four single stages per step), with
+// the default launch shapes; results do not depend on launch shapes, so they
+// are those of a handle created from the same parameters, bit for bit.
 #include <cstring>
 #include <mutex>
 
@@ -109,9 +110,9 @@ extern "C" int cosenu_step_noalloc(const cosenu_params *p, double *state, int64_
     d.ya = buf[1];
     d.yb = b + L.yb;
     for (int k = 0; k < 4; ++k) d.mom[k] = (double *)(b + L.mom[k]);
+    // default launch shapes (the tuning cache is not consulted: reading it
+    // allocates on the host); results do not depend on launch shapes
     const bool pairs = pair_supported(d);
-    const int tuned = tuned_seg(d.scheme, d.form, d.nz, d.nv, pairs);
-    set_shape(d, tuned > 0 ? tuned : default_seg_rows(d.nz, d.nv));
 
     // per-point constants, every element computed as the handle's table is
     const double s_nu = gaussian_norm(p->nv, p->quadrature, p->sigma_nu);

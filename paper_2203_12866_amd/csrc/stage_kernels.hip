@@ -41,6 +41,7 @@
 // and Y4 carry k1 and k3 and stay FP64) and every stage input is rounded to
 // FP32 before the stencil, so its right-hand side is evaluated on FP32 values.
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "cosenu_internal.h"
@@ -1031,6 +1032,298 @@ __device__ __forceinline__ void pair_body(const InstDesc &d, int vc, int sp, int
     }
 }
 
+// ---------------------------------------------------------------------------
+// A whole RK4 step in one launch for FD + KO with one row group per wave
+// (32 < nv <= 256, KO r <= 2).  The four stages march through one segment
+// together, each two rows behind the one before it (the stencil's reach):
+// at step s stage 1 produces Y2 row a1 = start + dir (s - 6), stage 2 Y3 row
+// a1 - 2 dir, stage 3 Y4 row a1 - 4 dir and stage 4 the new state at row
+// a1 - 6 dir.  Y2, Y3, Y4 and acc never leave the chip: each stage keeps the
+// last four rows of its output in registers as the next stage's window, the
+// moments of those rows are exchanged between the waves of the workgroup
+// through three LDS rings (as in the fused pairs: written at step s, read at
+// s + 2, one barrier per two steps), and acc, formed by stage 2 and consumed by
+// stage 4 four steps later, waits in a per-wave LDS queue.  Halos: the new
+// state over the segment needs Y4 two rows beyond it, Y3 four, Y2 six and y
+// eight, so each segment recomputes 6 + 4 + 2 rows of intermediate stages.
+// Every value and every moment partial is bitwise the one of four single
+// stages (same expressions, same summation order).
+//
+// Bytes per cell and step: the state read and written once, 2 x 64 = 128 in
+// both forms (32 per cell-velocity-stage update), plus the halo re-reads from
+// the caches.  The new state goes to the other state buffer and its moments to
+// the other moment buffer (d.ya, d.mom[1]): neighbouring workgroups still read
+// the old ones in their halos.
+// ---------------------------------------------------------------------------
+constexpr int kAccQ = 5;  // acc rows in flight between stage 2 and stage 4
+
+template <int FORM, bool REV, int PLOG>
+__device__ __forceinline__ void quad_body(const InstDesc &d, int vc, int sp, int segi, int l, int dir, double *lds,
+                                          double *xch, double *accq) {
+    using T = typename std::conditional<FORM == 0, double, float>::type;  // stencils, and Y3 as stored
+    constexpr int NC = 4, AH = 2, RING = kXchSlots;
+    const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
+    const int j = vc * kWave + l;
+    const bool lane_on = j < nv;
+    const int jl = lane_on ? j : nv - 1;
+    const int z0 = segi * d.seg, z1 = min(nz, z0 + d.seg);
+    const int nrows = z1 - z0;
+    const int start = dir > 0 ? z0 : z1 - 1;  // first row of stage 4
+    const int nsteps = nrows + 12;
+
+    const double v = d.vel[jl];
+    const double gl = lane_on ? d.g[jl] : 0.0;
+    const double agl = lane_on ? d.agb[jl] : 0.0;
+    const double ca = sp ? -agl : gl, cb = sp ? agl : gl;
+    const double sgn = sp ? -1.0 : 1.0;
+    const T cv = (T)(v * (1.0 / 12.0));
+    const T k0 = (T)d.ko[0], k1 = (T)d.ko[1];
+    const size_t plane = d.ps;
+    const int cofs = sp * NC;
+    const gchar *xb = (const gchar *)d.y + (size_t)cofs * plane * 8;  // the state
+    gchar *outb = (gchar *)d.ya + (size_t)cofs * plane * 8;          // the new state
+    const size_t p64 = plane * 8;
+    const gdouble *m_in = (const gdouble *)d.mom[0];
+    gdouble *m_out = (gdouble *)d.mom[1];
+    const int nparts = 2 * vchunks;
+    const int part = vc * 2 + sp;
+    const int pg = min(l / kPartLanes, 2), pp = min(l % kPartLanes, nparts - 1);
+    const bool p_on = l < 3 * kPartLanes && l % kPartLanes < nparts;
+    const int poff = pp * kMomQ + pg;
+
+    const double dzs = dir > 0 ? d.dz_inv : -d.dz_inv;
+    const double dt = d.dt, hdt = 0.5 * d.dt, dt6 = d.dt * (1.0 / 6.0);
+    const double third = 1.0 / 3.0;
+    const double mudv = d.mudv, h3vac = d.h3vac, hexvac = d.hexvac, lam = d.lam;
+
+    auto row1 = [&](int s) { return start + dir * (s - 6); };
+    auto load_x = [&](int row, double (&dst)[NC]) {
+        const uint32_t off = (uint32_t)(row * nv + jl) * 8u;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) dst[c] = ld<double>(xb + (size_t)c * p64, off);
+    };
+    struct Buf {
+        double nw[NC];  // y look-ahead row a1 + 2 dir
+        double pv[2];   // lane-distributed moment partials of y row a1
+        double y3[NC];  // y at the stage-3 row a1 - 4 dir (read again, from the caches)
+    };
+    auto issue = [&](int s, Buf &b) {
+        const int a = row1(s);
+        load_x(wrap_row(a + dir * AH, nz), b.nw);
+        const int ar = __builtin_amdgcn_readfirstlane(wrap_row(a, nz));
+        const gdouble *mp = m_in + (size_t)ar * nparts * kMomQ;
+        b.pv[0] = mp[poff];
+        b.pv[1] = mp[poff + 3];
+        load_x(wrap_row(a - 4 * dir, nz), b.y3);
+    };
+
+    double xw[NC][3];  // y rows a1 - dir, a1, a1 + dir
+    double lag[NC];    // y row a1 - 2 dir (the stage-2 row)
+    double z1w[NC][4]; // Y2 rows a1 - 3 dir .. a1
+    T z2w[NC][4];      // Y3 rows a2 - 3 dir .. a2, as the single stages store them
+    double z3w[NC][4]; // Y4 rows a3 - 3 dir .. a3
+    T f1[NC], f2[NC], f3[NC], f4[NC];  // fluxes on the faces behind the stage rows
+
+    auto flux = [&](auto x) -> T {  // FD + KO interface flux from four rows in dir order
+        return REV ? fd_ko_flux<T>(x(3), x(2), x(1), x(0), cv, k0, k1) : fd_ko_flux<T>(x(0), x(1), x(2), x(3), cv, k0, k1);
+    };
+    auto hamiltonian = [&](const double S[kMomQ], double &h3, double &hr, double &hi) {
+        const double A0 = S[0] - v * S[3];
+        const double A1 = S[1] - v * S[4];
+        const double A2 = S[2] - v * S[5];
+        h3 = h3vac + sgn * (lam + mudv * A0);
+        hr = hexvac + sgn * (mudv * A1);
+        hi = mudv * A2;
+    };
+    // the moments of a row, summed over the workgroup's waves from a ring slot
+    auto ring_sums = [&](int ring, int slot, double (&S)[kMomQ]) {
+        const double *xs = xch + (ring * RING + slot) * nparts * kMomQ;
+        const double pz[2] = {p_on ? xs[poff] : 0.0, p_on ? xs[poff + 3] : 0.0};
+        sum_row_parts_c<PLOG>(pz, S);
+    };
+    // this wave's moment totals of a produced row (the next stage sees FP32
+    // values in the FP32 form) into a ring slot
+    auto ring_put = [&](int ring, int slot, const double (&o)[NC]) {
+        double oo[NC], mt[kMomQ];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) oo[c] = lane_on ? (FORM == 1 ? (double)(float)o[c] : o[c]) : 0.0;
+        species_moment_terms(oo, ca, cb, v, mt);
+        const double t = wave_row_totals(mt, lds, l);
+        if ((l & 7) == 0 && (l >> 3) < kMomQ) xch[((ring * RING + slot) * nparts + part) * kMomQ + (l >> 3)] = t;
+    };
+    // one right-hand side: -i [H, rho] - (flux difference) / dz at the centre u.
+    // The flux difference is rounded in a statement of its own, as the single
+    // stages round it (one expression would let the compiler fuse it into the
+    // subtraction, and the results would differ in the last bit).
+    auto rhs = [&](const double (&S)[kMomQ], const T (&fn)[NC], T (&fprev)[NC], const double (&u)[NC],
+                   double (&kk)[NC]) {
+        double adv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            adv[c] = ((double)fn[c] - (double)fprev[c]) * dzs;
+            fprev[c] = fn[c];
+        }
+        double h3, hr, hi;
+        hamiltonian(S, h3, hr, hi);
+        minus_i_commutator(h3, hr, hi, u[0], u[1], u[2], u[3], kk[0], kk[1], kk[2], kk[3]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) kk[c] -= adv[c];
+    };
+
+    auto compute = [&](int s, const Buf &b, bool sync) {
+        // ---- stage 1: Y2 row a1 = y + dt/2 k1
+        {
+            T fn[NC];
+            double u[NC], kk[NC], S[kMomQ], z[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                fn[c] = flux([&](int m) -> T { return (T)(m < 3 ? xw[c][m] : b.nw[c]); });
+                u[c] = (double)(T)xw[c][1];
+            }
+            const double pz[2] = {p_on ? b.pv[0] : 0.0, p_on ? b.pv[1] : 0.0};
+            sum_row_parts_c<PLOG>(pz, S);
+            rhs(S, fn, f1, u, kk);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                z[c] = xw[c][1] + hdt * kk[c];
+                z1w[c][0] = z1w[c][1];
+                z1w[c][1] = z1w[c][2];
+                z1w[c][2] = z1w[c][3];
+                z1w[c][3] = z[c];
+            }
+            if (s >= 2 && s < nrows + 10) ring_put(0, s % RING, z);
+        }
+        if (sync) __syncthreads();
+        if (s == 3) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) f2[c] = flux([&](int m) -> T { return (T)z1w[c][m]; });
+        }
+        // ---- stage 2: Y3 row a2 = a1 - 2 dir = y + dt/2 k2; acc = (y + Y2 + dt k2) / 3
+        if (s >= 4) {
+            T fn[NC];
+            double u[NC], kk[NC], S[kMomQ], o[NC];
+            ring_sums(0, (s - 2) % RING, S);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                fn[c] = flux([&](int m) -> T { return (T)z1w[c][m]; });
+                u[c] = (double)(T)z1w[c][1];
+            }
+            rhs(S, fn, f2, u, kk);
+            double *aq = accq + (s % kAccQ) * NC * kWave + l;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                o[c] = lag[c] + hdt * kk[c];
+                aq[c * kWave] = ((lag[c] + z1w[c][1]) + dt * kk[c]) * third;
+                z2w[c][0] = z2w[c][1];
+                z2w[c][1] = z2w[c][2];
+                z2w[c][2] = z2w[c][3];
+                z2w[c][3] = (T)o[c];
+            }
+            if (s >= 6 && s < nrows + 10) ring_put(1, s % RING, o);
+        }
+        if (s == 7) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) f3[c] = flux([&](int m) -> T { return z2w[c][m]; });
+        }
+        // ---- stage 3: Y4 row a3 = a1 - 4 dir = y + dt k3
+        if (s >= 8) {
+            T fn[NC];
+            double u[NC], kk[NC], S[kMomQ], o[NC];
+            ring_sums(1, (s - 2) % RING, S);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                fn[c] = flux([&](int m) -> T { return z2w[c][m]; });
+                u[c] = (double)z2w[c][1];
+            }
+            rhs(S, fn, f3, u, kk);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                o[c] = b.y3[c] + dt * kk[c];
+                z3w[c][0] = z3w[c][1];
+                z3w[c][1] = z3w[c][2];
+                z3w[c][2] = z3w[c][3];
+                z3w[c][3] = o[c];
+            }
+            if (s >= 10 && s < nrows + 10) ring_put(2, s % RING, o);
+        }
+        if (s == 11) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) f4[c] = flux([&](int m) -> T { return (T)z3w[c][m]; });
+        }
+        // ---- stage 4: the new state at row a4 = a1 - 6 dir = (acc + Y4/3) + dt/6 k4
+        if (s >= 12) {
+            T fn[NC];
+            double u[NC], kk[NC], S[kMomQ], o[NC];
+            ring_sums(2, (s - 2) % RING, S);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                fn[c] = flux([&](int m) -> T { return (T)z3w[c][m]; });
+                u[c] = (double)(T)z3w[c][1];
+            }
+            rhs(S, fn, f4, u, kk);
+            const int brow = row1(s) - 6 * dir;  // in [z0, z1)
+            const uint32_t off = (uint32_t)(brow * nv + jl) * 8u;
+            const double *aq = accq + ((s - 4) % kAccQ) * NC * kWave + l;  // acc of this row, from step s - 4
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                o[c] = (aq[c * kWave] + z3w[c][1] * third) + dt6 * kk[c];
+                if (lane_on) st_nt<double>(outb + (size_t)c * p64, off, o[c]);
+                if (FORM == 1) o[c] = (double)(float)o[c];
+                if (!lane_on) o[c] = 0.0;
+            }
+            double mt[kMomQ];
+            species_moment_terms(o, ca, cb, v, mt);
+            wave_row_moments(mt, lds, l, m_out + (((size_t)brow * vchunks + vc) * 2 + sp) * kMomQ);
+        }
+        // slide the y window; the dropped row is the next step's stage-2 row
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            lag[c] = xw[c][0];
+            xw[c][0] = xw[c][1];
+            xw[c][1] = xw[c][2];
+            xw[c][2] = fresh_copy(b.nw[c]);
+        }
+    };
+
+    // prologue: y rows a1(0) - 2 dir .. a1(0) + dir, the loads of step 0, and
+    // the flux on the face behind row a1(0)
+    const int a0 = row1(0);
+    double low[NC];
+    load_x(wrap_row(a0 - 2 * dir, nz), low);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        double tmp[NC];
+        load_x(wrap_row(a0 + dir * (m - 1), nz), tmp);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xw[c][m] = tmp[c];
+    }
+    Buf bufA, bufB;
+    issue(0, bufA);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        f1[c] = flux([&](int m) -> T { return (T)(m == 0 ? low[c] : xw[c][m - 1]); });
+        f2[c] = f3[c] = f4[c] = T(0);
+        lag[c] = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            z1w[c][m] = 0.0;
+            z2w[c][m] = T(0);
+            z3w[c][m] = 0.0;
+        }
+    }
+    // The next step's loads are issued unconditionally (past the last step they
+    // read rows nobody uses, at most eight rows beyond the segment, inside one
+    // periodic wrap since nz >= 16), so the compiler's wait counts never wait
+    // for loads just issued.
+    for (int s = 0; s < nsteps; s += 2) {
+        issue(s + 1, bufB);
+        compute(s, bufA, false);
+        if (s + 1 >= nsteps) break;
+        issue(s + 2, bufA);
+        compute(s + 1, bufB, true);
+    }
+}
+
 // XCD-aware block order: the hardware deals workgroups round-robin to the 8
 // XCDs; renumber so that each XCD receives a contiguous range of tasks and
 // neighbouring segments (which share halo rows) meet in the same L2.  With
@@ -1057,24 +1350,28 @@ __device__ __forceinline__ double *wave_lds(double *pool) {
 template <int SCHEME, bool WR>
 constexpr int kMinWavesPerSimd = SCHEME == 0 ? (WR ? 4 : 3) : (WR ? 3 : 2);
 
+// Single-instance launches: workgroups of d.wpb waves (1, 2 or 4, a launch
+// shape the autotuner picks), with d.wpb wave scratches of dynamic LDS for the
+// wave-row moment reduction.
 template <int SCHEME, int FORM, int STAGE, bool WR>
 __global__ __launch_bounds__(kWave *kWavesPerBlock, (kMinWavesPerSimd<SCHEME, WR>)) void stage_kernel(InstDesc d) {
-    __shared__ __align__(16) double pool[WR ? kWavesPerBlock * kLdsPerWave : 2];
+    extern __shared__ __align__(16) double stage_pool[];
     const int lb = xcd_block(blockIdx.x, gridDim.x, (STAGE & 1) != 0);
-    const int wave = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane(lb * d.wpb + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & (kWave - 1);
     const int G = kWave >> d.lr_log2;
     const int task = wave * G + (lane >> d.lr_log2);
     if (wave * G >= d.ntasks) return;  // whole wave idle (uniform)
-    if constexpr (WR) stage_group<SCHEME, FORM, STAGE, true>(d, wave, lane, wave_lds<true>(pool));
+    if constexpr (WR) stage_group<SCHEME, FORM, STAGE, true>(d, wave, lane, wave_lds<true>(stage_pool));
     else stage_group<SCHEME, FORM, STAGE, false>(d, task, lane & ((1 << d.lr_log2) - 1), nullptr);
 }
 
 template <int FORM, bool WR>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) void moments_init_kernel(InstDesc d) {
-    __shared__ __align__(16) double pool[WR ? kWavesPerBlock * kLdsPerWave : 2];
+    extern __shared__ __align__(16) double stage_pool[];
+    double *pool = stage_pool;
     const int lb = xcd_block(blockIdx.x, gridDim.x, false);
-    const int wave = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane(lb * d.wpb + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & (kWave - 1);
     const int G = kWave >> d.lr_log2;
     const int task = wave * G + (lane >> d.lr_log2);
@@ -1120,6 +1417,24 @@ __global__ __launch_bounds__(kWave * (1 << PLOG), 3) void pair_kernel(InstDesc d
     else pair_body<FORM, PAIR, false, PLOG, FULL>(d, vc, sp, segi, lane, 1, lds, xch);
 }
 
+// A whole RK4 step per launch: one workgroup per segment, one wave per
+// (chunk, species); LDS holds each wave's scratch, the three moment rings and
+// each wave's acc queue.
+template <int FORM, int PLOG>
+__global__ __launch_bounds__(kWave * (1 << PLOG), 2) void quad_kernel(InstDesc d) {
+    extern __shared__ __align__(16) double quad_pool[];
+    const int nw = blockDim.x >> 6;  // 2 vchunks
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & (kWave - 1);
+    const int segi = xcd_block(blockIdx.x, gridDim.x, false);
+    double *lds = quad_pool + w * kLdsPerWave;
+    double *xch = quad_pool + nw * kLdsPerWave;
+    double *accq = xch + 3 * kXchSlots * nw * kMomQ + w * (kAccQ * 4 * kWave);
+    const int vc = w >> 1, sp = w & 1;
+    if (kAltDir && (segi & 1)) quad_body<FORM, true, PLOG>(d, vc, sp, segi, lane, -1, lds, xch, accq);
+    else quad_body<FORM, false, PLOG>(d, vc, sp, segi, lane, 1, lds, xch, accq);
+}
+
 // Batched fused stage pairs: a persistent grid of workgroups of 2 vchunks
 // waves walks a list of (instance, segment) tasks, sorted by decreasing cost
 // on the host, of instances that all have that many waves per segment.
@@ -1151,7 +1466,7 @@ int groups_per_wave(const InstDesc &d) { return kWave >> d.lr_log2; }
 int blocks_for(const InstDesc &d) {
     const int G = groups_per_wave(d);
     const int waves = (d.ntasks + G - 1) / G;
-    return (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    return (waves + d.wpb - 1) / d.wpb;
 }
 
 int row_blocks_for(const InstDesc &d) {
@@ -1161,13 +1476,19 @@ int row_blocks_for(const InstDesc &d) {
 }
 
 namespace {
+// dynamic LDS of a single-instance stage or moment launch: one wave scratch per
+// wave with one row group per wave, none otherwise
+size_t stage_shm_bytes(const InstDesc &d) {
+    return d.lr_log2 == 6 ? (size_t)d.wpb * kLdsPerWave * sizeof(double) : 0;
+}
 template <int SCHEME, int FORM, bool WR>
 hipError_t launch_stage_t(const InstDesc &d, int stage, dim3 grid, dim3 block, hipStream_t st) {
+    const size_t shm = stage_shm_bytes(d);
     switch (stage) {
-        case 0: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 0, WR>), grid, block, 0, st, d); break;
-        case 1: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 1, WR>), grid, block, 0, st, d); break;
-        case 2: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 2, WR>), grid, block, 0, st, d); break;
-        default: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 3, WR>), grid, block, 0, st, d); break;
+        case 0: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 0, WR>), grid, block, shm, st, d); break;
+        case 1: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 1, WR>), grid, block, shm, st, d); break;
+        case 2: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 2, WR>), grid, block, shm, st, d); break;
+        default: hipLaunchKernelGGL((stage_kernel<SCHEME, FORM, 3, WR>), grid, block, shm, st, d); break;
     }
     return hipGetLastError();
 }
@@ -1204,20 +1525,23 @@ hipError_t launch_batch_w(const InstDesc *dd, const WaveTask *tk, int nwt, int s
 }  // namespace
 
 hipError_t launch_stage(const InstDesc &d, int stage, int blocks, hipStream_t st) {
-    const dim3 grid(blocks), block(kWave * kWavesPerBlock);
+    if (d.wpb != 1 && d.wpb != 2 && d.wpb != 4) return hipErrorInvalidValue;
+    const dim3 grid(blocks), block(kWave * d.wpb);
     return d.lr_log2 == 6 ? launch_stage_w<true>(d, stage, grid, block, st)
                           : launch_stage_w<false>(d, stage, grid, block, st);
 }
 
 hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st) {
-    const dim3 grid(blocks), block(kWave * kWavesPerBlock);
+    if (d.wpb != 1 && d.wpb != 2 && d.wpb != 4) return hipErrorInvalidValue;
+    const dim3 grid(blocks), block(kWave * d.wpb);
+    const size_t shm = stage_shm_bytes(d);
     const bool wr = d.lr_log2 == 6;
     if (d.form == 0) {
-        if (wr) hipLaunchKernelGGL((moments_init_kernel<0, true>), grid, block, 0, st, d);
-        else hipLaunchKernelGGL((moments_init_kernel<0, false>), grid, block, 0, st, d);
+        if (wr) hipLaunchKernelGGL((moments_init_kernel<0, true>), grid, block, shm, st, d);
+        else hipLaunchKernelGGL((moments_init_kernel<0, false>), grid, block, shm, st, d);
     } else {
-        if (wr) hipLaunchKernelGGL((moments_init_kernel<1, true>), grid, block, 0, st, d);
-        else hipLaunchKernelGGL((moments_init_kernel<1, false>), grid, block, 0, st, d);
+        if (wr) hipLaunchKernelGGL((moments_init_kernel<1, true>), grid, block, shm, st, d);
+        else hipLaunchKernelGGL((moments_init_kernel<1, false>), grid, block, shm, st, d);
     }
     return hipGetLastError();
 }
@@ -1283,6 +1607,44 @@ hipError_t launch_pair(const InstDesc &d, int pair, hipStream_t st) {
     const dim3 grid(d.nseg), block(kWave * W);
     if (d.form == 0) return pair == 0 ? launch_pair_t<0, 0>(d, grid, block, shm, st) : launch_pair_t<0, 1>(d, grid, block, shm, st);
     return pair == 0 ? launch_pair_t<1, 0>(d, grid, block, shm, st) : launch_pair_t<1, 1>(d, grid, block, shm, st);
+}
+
+size_t quad_shm_bytes(int W) {
+    return (size_t)(W * kLdsPerWave + 3 * kXchSlots * W * kMomQ + W * kAccQ * 4 * kWave) * sizeof(double);
+}
+
+// The whole-step kernel needs nz >= 16 (its eight-row halos wrap once) and its
+// LDS within the device's per-workgroup limit (queried once per process).
+bool quad_supported(const InstDesc &d) {
+    static std::atomic<int> max_shm{-1};
+    if (!pair_supported(d) || d.nz < 16) return false;
+    int m = max_shm.load();
+    if (m < 0) {
+        int dev = 0, v = 0;
+        m = hipGetDevice(&dev) == hipSuccess &&
+                    hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess
+                ? v
+                : 65536;
+        max_shm.store(m);
+    }
+    return quad_shm_bytes(2 * d.vchunks) <= (size_t)m;
+}
+
+hipError_t launch_quad(const InstDesc &d, hipStream_t st) {
+    if (!quad_supported(d)) return hipErrorInvalidValue;
+    const int W = 2 * d.vchunks;
+    const size_t shm = quad_shm_bytes(W);
+    const dim3 grid(d.nseg), block(kWave * W);
+    if (d.form == 0) {
+        if (W <= 2) hipLaunchKernelGGL((quad_kernel<0, 1>), grid, block, shm, st, d);
+        else if (W <= 4) hipLaunchKernelGGL((quad_kernel<0, 2>), grid, block, shm, st, d);
+        else hipLaunchKernelGGL((quad_kernel<0, 3>), grid, block, shm, st, d);
+    } else {
+        if (W <= 2) hipLaunchKernelGGL((quad_kernel<1, 1>), grid, block, shm, st, d);
+        else if (W <= 4) hipLaunchKernelGGL((quad_kernel<1, 2>), grid, block, shm, st, d);
+        else hipLaunchKernelGGL((quad_kernel<1, 3>), grid, block, shm, st, d);
+    }
+    return hipGetLastError();
 }
 
 namespace {

@@ -217,7 +217,7 @@ def test_degenerate_calls_are_no_ops_or_rejected():
         assert L.cosenu_moments(s._h, p, 40 * 8 - 1) == cosenu.EINVAL
         assert L.cosenu_step(s._h, -1) == cosenu.EINVAL
         assert L.cosenu_set_seg_rows(s._h, -1) == cosenu.EINVAL
-        assert L.cosenu_set_fusion(s._h, 2) == cosenu.EINVAL
+        assert L.cosenu_set_fusion(s._h, 3) == cosenu.EINVAL and L.cosenu_set_fusion(s._h, -1) == cosenu.EINVAL
         # the handle still works and has not moved
         assert np.array_equal(s.get_rows(-3, 40), np.roll(y, 3, axis=1))
         s.step(1)
