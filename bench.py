@@ -52,9 +52,16 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, form: str):
-    """HBM bytes per stage launch from the committed rocprofv3 counter summary,
-    or None if it is missing or was taken on different kernel sources."""
+# VALU issue capacity of the chip: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64
+# instruction per 4 cycles per SIMD (16 lanes per cycle for FP64 and for
+# unpacked FP32), in billions of wave instructions per second
+PEAK_VALU_GINST = 256 * 4 * 2.4 / 4.0
+
+
+def profile_entry(workload: str, form: str):
+    """The committed rocprofv3 summary of one launch of this workload and form
+    (HBM bytes, VALU instructions), or None if it is missing or was taken on
+    different kernel sources."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         with open(path) as f:
@@ -63,8 +70,25 @@ def measured_traffic(workload: str, form: str):
         return None
     if t.get("kernel_sha") != kernel_hash():
         return None
-    e = t.get("entries", {}).get(f"{workload}/{form}")
+    return t.get("entries", {}).get(f"{workload}/{form}")
+
+
+def measured_traffic(workload: str, form: str):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    e = profile_entry(workload, form)
     return None if e is None else e.get("bytes_per_launch")
+
+
+def alu_roofline(workload: str, form: str, launch_s: float):
+    """VALU issue rate of the launches: the profiled VALU wave instructions per
+    launch over the launch duration measured in this run, against the chip's
+    issue capacity; None without a matching profile."""
+    e = profile_entry(workload, form)
+    if e is None or not e.get("valu_insts_per_launch"):
+        return None
+    g = e["valu_insts_per_launch"] / launch_s / 1e9
+    return {"achieved": g, "peak": PEAK_VALU_GINST, "unit": "G VALU wave64 instructions/s",
+            "frac": g / PEAK_VALU_GINST, "valu_insts_per_launch": e["valu_insts_per_launch"]}
 
 
 def tracked(w, c0, c1):
@@ -342,14 +366,20 @@ def run_workload(cosenu, torch, name, steps, warmup, seg, stage_steps, fused):
     for form, r in res.items():
         nl = r["launches"]
         suffix = {1: "/whole", 2: "/pairs", 4: ""}[nl]
+        hbm = {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+               "frac": r["achieved_gbps"] / PEAK_HBM_GBPS, "traffic": measured_traffic(name, form + suffix)}
+        alu = alu_roofline(name, form + suffix, r["launch_s"])
+        if nl == 1 and alu is not None:
+            # the whole step moves 32 B per update: VALU issue is its bound
+            roof = dict(bound="alu", **{k: v for k, v in alu.items()}, hbm=hbm)
+        else:
+            roof = dict(hbm, alu=alu)
+        roof.update({"kernel": kernel_name(w, nl, form), "launches_per_step": nl, "path": PATHS[nl],
+                     "avg_launch_us": r["launch_s"] * 1e6, "launch_us_eager": r["stage_us"]})
         forms[form] = {
             "value": r["updates"], "ms_per_step": r["wall"] * 1e3 / steps, "modelled_gbps": r["gbps_model"],
             "bytes_per_update": r["info"]["bytes_per_step"] / (cells * 4.0),
-            "roofline": {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                         "frac": r["achieved_gbps"] / PEAK_HBM_GBPS,
-                         "traffic": measured_traffic(name, form + suffix),
-                         "kernel": kernel_name(w, nl, form), "launches_per_step": nl, "path": PATHS[nl],
-                         "avg_launch_us": r["launch_s"] * 1e6, "launch_us_eager": r["stage_us"]},
+            "roofline": roof,
             "seg_rows": r["seg"],
         }
     return {

@@ -301,18 +301,39 @@ void fill_desc_constants(const cosenu_params &p, InstDesc &d) {
     set_shape(d, default_seg_rows(p.nz, p.nv));
 }
 
-// Sum of the per-task diagnostic partials (task order) into the public struct.
-void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vector<double> &part, double ee0n,
+// The diagnostics reduce over a fixed decomposition of the grid (kDiagSeg rows
+// per task), whatever launch shape the stage kernels use.
+InstDesc diag_desc(const InstDesc &d) {
+    InstDesc dd = d;
+    set_shape(dd, kDiagSeg);
+    return dd;
+}
+
+// Sum of the per-task diagnostic partials (task order, compensated) into the
+// public struct; dd is the descriptor the partials were reduced with.
+void finish_conserved(const cosenu_params &p, const InstDesc &dd, const std::vector<double> &part, double ee0n,
                       double ee0b, double t, int64_t step, cosenu_conserved_t *out) {
-    double a[kDiagQ] = {0};
-    for (int task = 0; task < d.nrowtasks; ++task) {
-        const double *q = &part[(size_t)task * kDiagQ];
+    double a[kDiagQ] = {0}, ac[kDiagQ] = {0};
+    auto comp_add = [](double &s, double &c, double x) {
+        const double u = s + x;
+        c += std::fabs(s) >= std::fabs(x) ? (s - u) + x : (x - u) + s;
+        s = u;
+    };
+    for (int task = 0; task < dd.nrowtasks; ++task) {
+        const double *q = &part[(size_t)task * kDiagPartial];
         for (int k = 0; k < kDiagQ; ++k) {
-            if (k == 10) a[k] = std::max(a[k], q[k]);
-            else a[k] += q[k];
+            if (k == 10) {
+                a[k] = std::max(a[k], q[k]);
+            } else if (k == 11) {
+                a[k] += q[k];
+            } else {
+                comp_add(a[k], ac[k], q[k]);
+                comp_add(a[k], ac[k], q[kDiagQ + k]);
+            }
         }
     }
-    const double cell = (p.L / p.nz) * d.dv;
+    for (int k = 0; k < 10; ++k) a[k] += ac[k];
+    const double cell = (p.L / p.nz) * dd.dv;
     std::memset(out, 0, sizeof *out);
     out->t = t;
     out->step = step;
@@ -461,7 +482,7 @@ struct cosenu_sim {
     double ee0_nu = 0.0, ee0_nubar = 0.0;
     size_t bytes = 0;
     std::vector<void *> allocs;
-    double *diag_part = nullptr;   // [max tasks][kDiagQ]
+    double *diag_part = nullptr;   // [max tasks][kDiagPartial]
     size_t diag_cap = 0;           // in tasks
     double *mom_out = nullptr;     // [nz][vchunks][8]
     int fusion = 1;                // cosenu_set_fusion: 0 single stages, 1 fused (default), 2 whole step preferred
@@ -601,12 +622,11 @@ int build_graphs(cosenu_sim *s) {
     return COSENU_OK;
 }
 
-int ensure_diag_capacity(cosenu_sim *s) {
-    if ((size_t)s->d.nrowtasks <= s->diag_cap) return COSENU_OK;
-    // the partial buffer is sized for the smallest segment length ever used
-    size_t need = (size_t)s->d.nrowtasks;
+int ensure_diag_capacity(cosenu_sim *s, const InstDesc &dd) {
+    if ((size_t)dd.nrowtasks <= s->diag_cap) return COSENU_OK;
+    size_t need = (size_t)dd.nrowtasks;
     void *p = nullptr;
-    int rc = sim_alloc(s, &p, need * kDiagQ * sizeof(double));
+    int rc = sim_alloc(s, &p, need * kDiagPartial * sizeof(double));
     if (rc) return rc;
     s->diag_part = (double *)p;
     s->diag_cap = need;
@@ -614,14 +634,15 @@ int ensure_diag_capacity(cosenu_sim *s) {
 }
 
 int compute_conserved(cosenu_sim *s, cosenu_conserved_t *out) {
-    int rc = ensure_diag_capacity(s);
+    const InstDesc dd = diag_desc(s->d);
+    int rc = ensure_diag_capacity(s, dd);
     if (rc) return rc;
-    HIPCHK(s, launch_diag(s->d, s->diag_part, row_blocks_for(s->d), s->stream));
-    std::vector<double> part((size_t)s->d.nrowtasks * kDiagQ);
+    HIPCHK(s, launch_diag(dd, s->diag_part, row_blocks_for(dd), s->stream));
+    std::vector<double> part((size_t)dd.nrowtasks * kDiagPartial);
     HIPCHK(s, hipMemcpyAsync(part.data(), s->diag_part, part.size() * sizeof(double), hipMemcpyDeviceToHost,
                              s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    finish_conserved(s->prm, s->d, part, s->ee0_nu, s->ee0_nubar, s->t, s->step, out);
+    finish_conserved(s->prm, dd, part, s->ee0_nu, s->ee0_nubar, s->t, s->step, out);
     return COSENU_OK;
 }
 
@@ -762,7 +783,7 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) try {
     {
         // diagnostics partials sized for the finest launch shape the tuner may pick (seg >= 1)
         const size_t cap = (size_t)nz * s->d.vchunks;
-        if ((rc = sim_alloc(s, &ptr, cap * kDiagQ * sizeof(double)))) return fail(rc);
+        if ((rc = sim_alloc(s, &ptr, cap * kDiagPartial * sizeof(double)))) return fail(rc);
         s->diag_part = (double *)ptr;
         s->diag_cap = cap;
     }

@@ -34,7 +34,9 @@ double bytes_per_cell_step_whole(int form);
 void fill_desc_constants(const cosenu_params &p, InstDesc &d);
 hipError_t moments_to_host(const InstDesc &d, double *scratch, hipStream_t st, double *out);
 hipError_t rows_to_host(const InstDesc &d, int64_t z0, int nrows, hipStream_t st, double *out);
-void finish_conserved(const cosenu_params &p, const InstDesc &d, const std::vector<double> &part, double ee0n,
+// the descriptor of the diagnostics reduction: a fixed decomposition (kDiagSeg rows per task)
+InstDesc diag_desc(const InstDesc &d);
+void finish_conserved(const cosenu_params &p, const InstDesc &dd, const std::vector<double> &part, double ee0n,
                       double ee0b, double t, int64_t step, cosenu_conserved_t *out);
 // Tuned launch shapes per device and (kernel variant, form, nv, nz bucket);
 // zeros where not tuned.  Kept for the process, and in the file named by

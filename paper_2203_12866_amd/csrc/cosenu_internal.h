@@ -13,7 +13,11 @@ constexpr int kWavesPerBlock = 4;   // default (and largest) waves per stage wor
                                     // batch kernels always run 4 (256 threads)
 constexpr int kMomQ = 6;            // reduced quantities per row and part:
                                     //   sum D3, sum ReDex, sum ImDex, and the same times v
-constexpr int kDiagQ = 12;         // per-task partials of the conserved-quantity kernel
+constexpr int kDiagQ = 12;         // per-task quantities of the conserved-quantity kernel
+constexpr int kDiagPartial = 22;   // per-task doubles it writes: kDiagQ values, then the compensations
+                                   //   of the 10 compensated sums
+constexpr int kDiagSeg = 16;       // rows per task of the conserved-quantity reduction, fixed so that
+                                   //   results do not depend on the stage kernels' launch shape
 constexpr int kPlanePad = 544;      // elements between planes beyond nz*nv (4352 B in FP64, 2176 B
                                     // in FP32: 128-byte aligned, off the power-of-two strides)
 constexpr int kLdsQStride = 68;     // doubles between quantity rows of a wave's moment scratch
@@ -86,7 +90,8 @@ hipError_t launch_batch_pair(const InstDesc *d_descs, const WaveTask *d_tasks, i
                              int blocks, hipStream_t st);
 int batch_pair_blocks_per_cu(int form, int W);
 // ---- diagnostics (diag_kernels.hip) ----------------------------------------
-// per (segment, chunk) partials [nrowtasks][kDiagQ]:
+// per (segment, chunk) partials [nrowtasks][kDiagPartial] (sums with their
+// Neumaier compensations in slots kDiagQ ..):
 //   0..3 M0 (trace, x, y, z) summed g P - alpha gbar Pbar~ (without dz dv)
 //   4 N_nu, 5 N_nubar (sum g Tr rho, sum gbar Tr rhobar), 6 sum g |dP_nu|, 7 sum g,
 //   8 sum g rho_ee, 9 sum gbar rhobar_ee, 10 max |dP| over both species, 11 non-finite count

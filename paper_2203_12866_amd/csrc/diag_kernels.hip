@@ -3,7 +3,10 @@
 // moments of D = g rho - alpha gbar rhobar^*.  Same task decomposition as the
 // stage kernels (row groups of lanes over v, segments of rows over z); each
 // lane accumulates its bin down the segment, then the group reduces with an
-// xor butterfly and lane 0 writes one partial per task.
+// xor butterfly and lane 0 writes one partial per task.  The sums of the
+// conserved quantities are compensated (Neumaier): a drift of 1e-15 relative
+// has to be measurable over 5e8 cells, where plain FP64 summation would leave
+// rounding noise near 1e-13.
 #include <algorithm>
 #include <cmath>
 
@@ -15,6 +18,26 @@ namespace {
 __device__ __forceinline__ double group_sum(double x, int lr_log2) {
     for (int off = (1 << lr_log2) >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
     return x;
+}
+// Compensated accumulation: s + c carries the sum to about twice FP64
+// precision (Neumaier's variant of Kahan summation).
+__device__ __forceinline__ void comp_add(double &s, double &c, double x) {
+    const double t = s + x;
+    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+}
+// the same over the lanes of a row group: every lane ends with the group's (s, c)
+__device__ __forceinline__ void group_comp_sum(double &s, double &c, int lr_log2) {
+    for (int off = (1 << lr_log2) >> 1; off > 0; off >>= 1) {
+        const double so = __shfl_xor(s, off, kWave), co = __shfl_xor(c, off, kWave);
+        // both lanes of a pair form the same sum (operands in lane order)
+        const bool lo = (threadIdx.x & off) == 0;
+        double a = lo ? s : so, ca = lo ? c : co;
+        const double b = lo ? so : s, cb = lo ? co : c;
+        comp_add(a, ca, b);
+        s = a;
+        c = ca + cb;
+    }
 }
 __device__ __forceinline__ double group_max(double x, int lr_log2) {
     for (int off = (1 << lr_log2) >> 1; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, kWave));
@@ -39,9 +62,9 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void diag_kernel(InstDesc d,
     const int z1 = task_ok ? min(nz, z0 + d.seg) : z0;
     const double g = d.g[jl], gb = d.gb[jl], ag = d.agb[jl];
     const size_t plane = d.ps;
-    double a[kDiagQ];
+    double a[kDiagQ], ac[kDiagQ];  // sums (or max / count) and their compensations
 #pragma unroll
-    for (int q = 0; q < kDiagQ; ++q) a[q] = 0.0;
+    for (int q = 0; q < kDiagQ; ++q) a[q] = ac[q] = 0.0;
     if (lane_on) {
         for (int i = z0; i < z1; ++i) {
             const size_t at = (size_t)i * nv + jl;
@@ -54,26 +77,33 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void diag_kernel(InstDesc d,
             // polarisation vectors: rho = (P0 + P.sigma)/2; Pbar~ belongs to rhobar^*
             const double P0 = o[0] + o[1], P1 = 2.0 * o[2], P2 = -2.0 * o[3], P3 = o[0] - o[1];
             const double Q0 = o[4] + o[5], Q1 = 2.0 * o[6], Q2 = 2.0 * o[7], Q3 = o[4] - o[5];
-            a[0] += g * P0 - ag * Q0;
-            a[1] += g * P1 - ag * Q1;
-            a[2] += g * P2 - ag * Q2;
-            a[3] += g * P3 - ag * Q3;
-            a[4] += g * P0;
-            a[5] += gb * Q0;
+            comp_add(a[0], ac[0], g * P0 - ag * Q0);
+            comp_add(a[1], ac[1], g * P1 - ag * Q1);
+            comp_add(a[2], ac[2], g * P2 - ag * Q2);
+            comp_add(a[3], ac[3], g * P3 - ag * Q3);
+            comp_add(a[4], ac[4], g * P0);
+            comp_add(a[5], ac[5], gb * Q0);
             const double dpn = fabs(sqrt(P1 * P1 + P2 * P2 + P3 * P3) - 1.0);
             const double dpb = fabs(sqrt(Q1 * Q1 + Q2 * Q2 + Q3 * Q3) - 1.0);
-            a[6] += g * dpn;
-            a[7] += g;
-            a[8] += g * o[0];
-            a[9] += gb * o[4];
+            comp_add(a[6], ac[6], g * dpn);
+            comp_add(a[7], ac[7], g);
+            comp_add(a[8], ac[8], g * o[0]);
+            comp_add(a[9], ac[9], gb * o[4]);
             a[10] = fmax(a[10], fmax(dpn, dpb));
         }
     }
 #pragma unroll
-    for (int q = 0; q < kDiagQ; ++q) a[q] = (q == 10) ? group_max(a[q], d.lr_log2) : group_sum(a[q], d.lr_log2);
+    for (int q = 0; q < kDiagQ; ++q) {
+        if (q == 10) a[q] = group_max(a[q], d.lr_log2);
+        else if (q == 11) a[q] = group_sum(a[q], d.lr_log2);  // a count: exact
+        else group_comp_sum(a[q], ac[q], d.lr_log2);
+    }
     if (task_ok && l == 0) {
+        // sums as (value, compensation) pairs: kDiagQ values, then the compensations of the first 10
 #pragma unroll
-        for (int q = 0; q < kDiagQ; ++q) partials[(size_t)task * kDiagQ + q] = a[q];
+        for (int q = 0; q < kDiagQ; ++q) partials[(size_t)task * kDiagPartial + q] = a[q];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) partials[(size_t)task * kDiagPartial + kDiagQ + q] = ac[q];
     }
 }
 

@@ -263,3 +263,23 @@ def test_batch_survives_failed_autotune():
         b.step(0)
         for i in range(len(ws)):
             assert np.array_equal(b.get_state(i), solo[i]), i
+
+
+def test_conserved_quantities_independent_of_launch_shape():
+    """The diagnostics reduce over a fixed decomposition with compensated sums,
+    so the same state gives the same conserved quantities, bit for bit,
+    whatever segment length, workgroup size or path the stage kernels use (a
+    drift measured across an autotuning is then the state's, not the sum's)."""
+    nz, nv = 1000, 128
+    w = dict(wl.small_fd(3), nz=nz, nv=nv, L=100.0, omega=0.05, lam=0.3)
+    y0 = wl.random_unit_state(nz, nv, seed=5)
+    with cosenu.Sim(w) as s:
+        s.set_state(y0)
+        ref = s.conserved()
+        for seg in (1, 7, 64, nz):
+            s.set_seg_rows(seg)
+            assert s.conserved() == ref, seg
+        s.set_fusion(2)
+        assert s.conserved() == ref
+        s.autotune()
+        assert s.conserved() == ref
