@@ -267,7 +267,8 @@ def cpu_baseline(cosenu, w, budget_s):
 
 # kernel variants of a batch, in the order cosenu_batch_autotune reports them
 BATCH_VARIANTS = ["fd_nv<=32", "fd_nv>32", "weno7_nv<=32", "weno7_nv>32", "fd_ko3_nv<=32", "fd_ko3_nv>32",
-                  "fd_pairs_w2", "fd_pairs_w4", "fd_pairs_w6", "fd_pairs_w8"]
+                  "fd_pairs_w2", "fd_pairs_w4", "fd_pairs_w6", "fd_pairs_w8",
+                  "fd_whole_w2", "fd_whole_w4", "fd_whole_w6", "fd_whole_w8"]
 
 
 def run_batch(cosenu, torch, insts, steps, warmup):
@@ -292,7 +293,8 @@ def run_batch(cosenu, torch, insts, steps, warmup):
     bytes_step = sum(inf["bytes_per_step"] for inf in infos)
     launch_s = ev_ms / (4.0 * steps) / 1e3
     fused = sum(1 for inf in infos if inf["launches_per_step"] == 2)
-    return dict(wall=wall, ev_ms=ev_ms, cells=cells, updates=cells * 4.0 * steps / wall, fused=fused,
+    whole = sum(1 for inf in infos if inf["launches_per_step"] == 1)
+    return dict(wall=wall, ev_ms=ev_ms, cells=cells, updates=cells * 4.0 * steps / wall, fused=fused, whole=whole,
                 gbps_model=bytes_step * steps / wall / 1e9, bytes_step=bytes_step,
                 achieved_gbps=bytes_step / 4.0 / launch_s / 1e9, launch_s=launch_s,
                 segs=segs, tune_s=tune_s, nonfinite=bad)
@@ -307,7 +309,7 @@ def batch_summary(r, insts, steps):
                    "cells": r["cells"], "nz_range": [min(w["nz"] for w in insts), max(w["nz"] for w in insts)],
                    "nv_set": sorted({w["nv"] for w in insts}), "form": "FP32 stencils, FP64 moments/commutator/RK4",
                    "seg_rows_per_variant": {k: v for k, v in zip(BATCH_VARIANTS, r["segs"]) if v},
-                   "fused_pair_instances": r["fused"]},
+                   "fused_pair_instances": r["fused"], "whole_step_instances": r["whole"]},
         "modelled_gbps": r["gbps_model"],
         "bytes_per_update": r["bytes_step"] / (r["cells"] * 4.0),
         # the variants' launch chains overlap, so there is no single launch
@@ -315,8 +317,9 @@ def batch_summary(r, insts, steps):
         "roofline": {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": r["achieved_gbps"] / PEAK_HBM_GBPS,
                      "traffic": measured_traffic("batch_64", "fp32acc"),
-                     "kernel": "batch_pair_kernel (FD fused pairs) and batch_stage_kernel (WENO7, FD nv<=32), "
-                               "one launch chain per variant, concurrent graph branches",
+                     "kernel": "batch_quad_kernel / batch_pair_kernel (FD whole steps or fused pairs) and "
+                               "batch_stage_kernel (WENO7, FD nv<=32), one launch chain per variant, concurrent "
+                               "graph branches",
                      "step_us": r["ev_ms"] * 1e3 / steps},
         "nonfinite_instances": r["nonfinite"],
         "autotune_s": r["tune_s"],

@@ -288,10 +288,11 @@ int cosenu_step_noalloc(const cosenu_params *p, double *state, int64_t nsteps, v
  * n independent simulations of any sizes and schemes (one precision for the
  * whole batch, taken from p[0]) advanced together: per RK4 step, each kernel
  * variant present runs persistent launches walking a work list (four single
- * stages, or two fused stage pairs for FD + KO with ko_order <= 2 and
- * 32 < nv <= 256, as cosenu_sim runs them), and steps of the whole batch are
- * HIP graphs.  Instance i behaves exactly like a cosenu_sim created from p[i]
- * (bit for bit, whatever the launch shapes).                                */
+ * stages; for FD + KO with ko_order <= 2 and 32 < nv <= 256 two fused stage
+ * pairs, or one whole step once the batch autotuner or a tuning of the shape
+ * chose it), and steps of the whole batch are HIP graphs.  Instance i behaves
+ * exactly like a cosenu_sim created from p[i] (bit for bit, whatever the
+ * paths and launch shapes).                                                 */
 int cosenu_batch_create(const cosenu_params *p, int32_t n, cosenu_batch **out);
 void cosenu_batch_destroy(cosenu_batch *b);
 int cosenu_batch_step(cosenu_batch *b, int64_t nsteps);
@@ -309,15 +310,18 @@ int cosenu_batch_get_rows(cosenu_batch *b, int32_t i, int64_t z0, int32_t nrows,
 int cosenu_batch_info(cosenu_batch *b, int32_t i, cosenu_info_t *out);
 int cosenu_batch_time_steps(cosenu_batch *b, int64_t nsteps, double *ms);
 /* Batch autotuner: chooses the segment length of every kernel variant of the
- * batch by timing that variant alone (single stages 1-3, or both fused pairs)
- * for seg in {4, 6, 8, 11, ..., 128} (about sqrt(2) apart); every instance of
- * a variant takes the same length (at most its nz).  Variants: 2*k + (nv > 32)
- * for single stages, k = 0 FD with ko_order <= 2, 1 WENO7, 2 FD with ko_order
- * 3; 6 + vchunks - 1 for fused pairs (vchunks = ceil(nv / 64) = 1 .. 4).
- * Then rebuilds the task lists and re-captures the step graphs.  States,
- * clocks and results are unchanged (results do not depend on the segment
- * length).  seg_rows, if not NULL, receives 10 values (0 for variants absent
- * from the batch).  Synchronises the handle's stream.                       */
+ * batch by timing that variant alone (single stages 1-3, or a whole step of
+ * the fused pairs or the whole-step kernel) for seg in {4, 6, 8, 11, ..., 128}
+ * (about sqrt(2) apart); every instance of a variant takes the same length (at
+ * most its nz).  The FD + KO instances that can fuse are timed as fused pairs
+ * and as whole steps, and each group with the same vchunks takes the faster
+ * path.  Variants: 2*k + (nv > 32) for single stages, k = 0 FD with ko_order
+ * <= 2, 1 WENO7, 2 FD with ko_order 3; 6 + vchunks - 1 for fused pairs and
+ * 10 + vchunks - 1 for whole steps (vchunks = ceil(nv / 64) = 1 .. 4).  Then
+ * rebuilds the task lists and re-captures the step graphs.  States, clocks
+ * and results are unchanged (results do not depend on paths or segment
+ * lengths).  seg_rows, if not NULL, receives 14 values (0 for variants the
+ * batch does not run).  Synchronises the handle's stream.                   */
 int cosenu_batch_autotune(cosenu_batch *b, int32_t *seg_rows);
 const char *cosenu_batch_last_error(const cosenu_batch *b);
 

@@ -395,7 +395,7 @@ class Batch:
     def autotune(self) -> list:
         """Segment length per kernel variant: 2*k + (nv > 32) for single stages,
         k = 0 FD (KO r <= 2), 1 WENO7, 2 FD (KO r = 3); 6 + vchunks - 1 for
-        fused stage pairs; 0 where absent."""
-        segs = (ctypes.c_int32 * 10)()
+        fused stage pairs; 10 + vchunks - 1 for whole steps; 0 where absent."""
+        segs = (ctypes.c_int32 * 14)()
         self._check(_lib().cosenu_batch_autotune(self._h, segs), "cosenu_batch_autotune")
         return list(segs)

@@ -89,6 +89,10 @@ hipError_t launch_quad(const InstDesc &d, hipStream_t st);
 hipError_t launch_batch_pair(const InstDesc *d_descs, const WaveTask *d_tasks, int ntasks, int form, int pair, int W,
                              int blocks, hipStream_t st);
 int batch_pair_blocks_per_cu(int form, int W);
+// batched whole steps, the same task lists as the fused pairs
+hipError_t launch_batch_quad(const InstDesc *d_descs, const WaveTask *d_tasks, int ntasks, int form, int W, int blocks,
+                             hipStream_t st);
+int batch_quad_blocks_per_cu(int form, int W);
 // ---- diagnostics (diag_kernels.hip) ----------------------------------------
 // per (segment, chunk) partials [nrowtasks][kDiagPartial] (sums with their
 // Neumaier compensations in slots kDiagQ ..):

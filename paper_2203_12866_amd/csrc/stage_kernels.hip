@@ -1435,6 +1435,31 @@ __global__ __launch_bounds__(kWave * (1 << PLOG), 2) void quad_kernel(InstDesc d
     else quad_body<FORM, false, PLOG>(d, vc, sp, segi, lane, 1, lds, xch, accq);
 }
 
+// Batched whole steps: a persistent grid of workgroups of 2 vchunks waves
+// walks a list of (instance, segment) tasks, sorted by decreasing cost on the
+// host, of instances that all have that many waves per segment.
+template <int FORM, int PLOG>
+__global__ __launch_bounds__(kWave * (1 << PLOG), 2) void batch_quad_kernel(const InstDesc *__restrict__ descs,
+                                                                             const WaveTask *__restrict__ tasks,
+                                                                             int ntasks) {
+    extern __shared__ __align__(16) double quad_pool[];
+    const int nw = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & (kWave - 1);
+    double *lds = quad_pool + w * kLdsPerWave;
+    double *xch = quad_pool + nw * kLdsPerWave;
+    double *accq = xch + 3 * kXchSlots * nw * kMomQ + w * (kAccQ * 4 * kWave);
+    const int vc = w >> 1, sp = w & 1;
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const WaveTask tk = tasks[t];
+        const InstDesc &d = descs[tk.inst];
+        const int segi = tk.task0;
+        if (kAltDir && (segi & 1)) quad_body<FORM, true, PLOG>(d, vc, sp, segi, lane, -1, lds, xch, accq);
+        else quad_body<FORM, false, PLOG>(d, vc, sp, segi, lane, 1, lds, xch, accq);
+        __syncthreads();  // the next task rewrites the LDS rings and queues from their first slots
+    }
+}
+
 // Batched fused stage pairs: a persistent grid of workgroups of 2 vchunks
 // waves walks a list of (instance, segment) tasks, sorted by decreasing cost
 // on the host, of instances that all have that many waves per segment.
@@ -1661,6 +1686,33 @@ const void *batch_pair_fn_any(int form, int pair, int W) {
     return W <= 2 ? batch_pair_fn_p<1>(form, pair) : W <= 4 ? batch_pair_fn_p<2>(form, pair) : batch_pair_fn_p<3>(form, pair);
 }
 }  // namespace
+
+namespace {
+template <int FORM>
+const void *batch_quad_fn(int W) {
+    return W <= 2 ? reinterpret_cast<const void *>(batch_quad_kernel<FORM, 1>)
+         : W <= 4 ? reinterpret_cast<const void *>(batch_quad_kernel<FORM, 2>)
+                  : reinterpret_cast<const void *>(batch_quad_kernel<FORM, 3>);
+}
+const void *batch_quad_fn_any(int form, int W) { return form == 0 ? batch_quad_fn<0>(W) : batch_quad_fn<1>(W); }
+}  // namespace
+
+hipError_t launch_batch_quad(const InstDesc *d_descs, const WaveTask *d_tasks, int ntasks, int form, int W, int blocks,
+                             hipStream_t st) {
+    if (W < 2 || W > 8 || (W & 1)) return hipErrorInvalidValue;
+    const void *fn = batch_quad_fn_any(form, W);
+    void *args[] = {(void *)&d_descs, (void *)&d_tasks, (void *)&ntasks};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(kWave * W), args, quad_shm_bytes(W), st);
+}
+
+int batch_quad_blocks_per_cu(int form, int W) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_quad_fn_any(form, W), kWave * W, quad_shm_bytes(W)) ==
+            hipSuccess &&
+        nb > 0)
+        return nb;
+    return 1;
+}
 
 hipError_t launch_batch_pair(const InstDesc *d_descs, const WaveTask *d_tasks, int ntasks, int form, int pair, int W,
                              int blocks, hipStream_t st) {

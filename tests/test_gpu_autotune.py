@@ -105,3 +105,46 @@ def test_forced_shapes_from_cache_are_bitwise(tmp_path, case):
     else:
         assert nl == 4 and info["seg_rows"] == ss and info["waves_per_workgroup"] == wpb
     assert np.array_equal(got, _solo(w, 9))
+
+
+BATCH_CHILD = r"""
+import json, sys
+import numpy as np
+sys.path.insert(0, {root!r})
+from paper_2203_12866_amd import cosenu
+ws, steps, out = json.loads(sys.argv[1]), int(sys.argv[2]), sys.argv[3]
+with cosenu.Batch(ws) as b:
+    b.step(steps)
+    launches = [b.info(i)["launches_per_step"] for i in range(len(ws))]
+    np.savez(out, *[b.get_state(i) for i in range(len(ws))])
+print(json.dumps(launches))
+"""
+
+
+def test_batch_whole_steps_from_cache_are_bitwise(tmp_path):
+    """A batch whose FD + KO shapes were tuned to the whole step (forced
+    through the cache file) runs them with the batched whole-step kernel, next
+    to fused pairs and single stages; every instance equals its solo run."""
+    cache = str(tmp_path / "tune.txt")
+    _child(dict(wl.small_fd(1), nz=64, nv=64, L=10.0), True, 1, str(tmp_path / "t.npy"), cache)
+    dev = [ln for ln in open(cache) if not ln.startswith("#")][0].split()[0]
+    ws = [dict(wl.small_fd(21), nz=300, nv=128, L=30.0),            # whole step (forced)
+          dict(wl.small_fd(22), nz=77, nv=256, L=20.0),             # whole step (forced), 8 waves
+          dict(wl.small_fd(23), nz=129, nv=65, L=25.0),             # fused pairs (not in the cache)
+          dict(wl.small_fv(24), nz=64, nv=96, L=10.0, omega=0.1),   # WENO7 single stages
+          dict(wl.small_fd(25), nz=15, nv=64, L=5.0)]               # nz < 16: fused pairs
+    with open(cache, "w") as f:
+        for w, seg in ((ws[0], 13), (ws[1], 7), (ws[4], 5)):
+            f.write(f"{dev} 0 0 {w['nv']} {_bucket(w['nz'])} 0 {seg} 0 0 2\n")
+    env = dict(os.environ, COSENU_TUNE_CACHE=cache)
+    out = str(tmp_path / "b.npz")
+    r = subprocess.run([sys.executable, "-c", BATCH_CHILD.format(root=ROOT), json.dumps(ws), "7", out], env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    launches = json.loads(r.stdout.strip().splitlines()[-1])
+    print(f"launches per step: {launches}")
+    assert launches == [1, 1, 2, 4, 2]
+    got = np.load(out)
+    for i, w in enumerate(ws):
+        ref = _solo(w, 7)
+        assert np.array_equal(got[f"arr_{i}"], ref), i

@@ -101,7 +101,10 @@ def test_batch_autotune_keeps_states_and_results():
         segs = b.autotune()
         assert all(np.array_equal(b.get_state(i), before[i]) for i in range(len(insts)))
         # WENO7 single stages (nv 32: variant 2, nv 256: 3); FD fused pairs (nv 64: 6, nv 128: 7)
-        assert [k for k, s in enumerate(segs) if s > 0] == [2, 3, 6, 7], segs
+        # or whole steps (10, 11), whichever the tuner found faster per group
+        present = [k for k, s in enumerate(segs) if s > 0]
+        assert len(segs) == 14 and present[:2] == [2, 3] and len(present) == 4, segs
+        assert present[2] in (6, 10) and present[3] in (7, 11), segs
         b.step(7)
         got = [b.get_state(i) for i in range(len(insts))]
     for w, g in zip(insts, got):
