@@ -161,32 +161,48 @@ __device__ __forceinline__ float weno_combine<float>(float s0, float s1, float s
     return num * __builtin_amdgcn_rcpf(den);
 }
 
-// WENO7 reconstruction at i+1/2 from a_k = f_{i-3+k}, k = 0..6 (Appendix A).
+// WENO7 reconstruction at i+1/2 from a_k = u_{i-3+k}, k = 0..6 (Appendix A),
+// returned times v: v a_3 + (v/12) * combine(12 q_r), with tv = v, tv12 = v/12.
 // Computed on the stencil shifted by its centre value a_3: the smoothness
 // indicators annihilate constants and every candidate reproduces them, so the
 // shift is exact algebra; it removes the large common part before the
-// quadratic forms (essential in FP32) and drops the terms in a_3.
+// quadratic forms (essential in FP32) and drops the terms in a_3.  The
+// candidates' common factor 1/12 leaves the normalised combination and joins
+// v in the final scaling, and eps enters each indicator's last fused
+// multiply-add.
 template <typename T>
-__device__ __forceinline__ T weno7_flux(T a0, T a1, T a2, T a3, T a4, T a5, T a6, T eps) {
+__device__ __forceinline__ T fma_t(T a, T b, T c);
+template <>
+__device__ __forceinline__ double fma_t<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <>
+__device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// One smoothness indicator plus eps, for the quadratic form
+// x (c0 x + c1 y + c2 z) + y (c3 y + c4 z) + c5 z^2 of eq:Si4 written as a
+// chain of fused multiply-adds.
+template <typename T>
+__device__ __forceinline__ T indicator(T x, T y, T z, T c0, T c1, T c2, T c3, T c4, T c5, T eps) {
+    const T ix = fma_t<T>(c2, z, fma_t<T>(c1, y, c0 * x));
+    const T iy = fma_t<T>(c4, z, c3 * y);
+    return fma_t<T>(x, ix, fma_t<T>(y, iy, fma_t<T>(c5 * z, z, eps)));
+}
+
+template <typename T>
+__device__ __forceinline__ T weno7_flux(T a0, T a1, T a2, T a3, T a4, T a5, T a6, T eps, T tv, T tv12) {
     const T b0 = a0 - a3, b1 = a1 - a3, b2 = a2 - a3;
     const T b4 = a4 - a3, b5 = a5 - a3, b6 = a6 - a3;
-    const T k12 = T(1.0 / 12.0);
-    // fourth-order candidates on S_0..S_3 (eq:f4s), minus a_3
-    const T q0 = (T(13) * b4 - T(5) * b5 + b6) * k12;
-    const T q1 = (T(7) * b4 - b2 - b5) * k12;
-    const T q2 = (b1 - T(5) * b2 + T(3) * b4) * k12;
-    const T q3 = (T(13) * b1 - T(3) * b0 - T(23) * b2) * k12;
-    // smoothness indicators (eq:Si4) with the centre value removed
-    const T si0 = b4 * (T(11003) * b4 - T(17246) * b5 + T(4642) * b6) + b5 * (T(7043) * b5 - T(3882) * b6) +
-                  T(547) * (b6 * b6);
-    const T si1 = b2 * (T(547) * b2 + T(1922) * b4 - T(494) * b5) + b4 * (T(2843) * b4 - T(1642) * b5) +
-                  T(267) * (b5 * b5);
-    const T si2 = b1 * (T(267) * b1 - T(1642) * b2 - T(494) * b4) + b2 * (T(2843) * b2 + T(1922) * b4) +
-                  T(547) * (b4 * b4);
-    const T si3 = b0 * (T(547) * b0 - T(3882) * b1 + T(4642) * b2) + b1 * (T(7043) * b1 - T(17246) * b2) +
-                  T(11003) * (b2 * b2);
-    const T e0 = si0 + eps, e1 = si1 + eps, e2 = si2 + eps, e3 = si3 + eps;
-    return a3 + weno_combine<T>(e0 * e0, e1 * e1, e2 * e2, e3 * e3, q0, q1, q2, q3);
+    // twelve times the fourth-order candidates on S_0..S_3 (eq:f4s), minus 12 a_3
+    const T q0 = fma_t<T>(T(13), b4, fma_t<T>(T(-5), b5, b6));
+    const T q1 = fma_t<T>(T(7), b4, -(b2 + b5));
+    const T q2 = fma_t<T>(T(3), b4, fma_t<T>(T(-5), b2, b1));
+    const T q3 = fma_t<T>(T(13), b1, fma_t<T>(T(-3), b0, T(-23) * b2));
+    // smoothness indicators (eq:Si4) with the centre value removed, plus eps
+    const T e0 = indicator<T>(b4, b5, b6, T(11003), T(-17246), T(4642), T(7043), T(-3882), T(547), eps);
+    const T e1 = indicator<T>(b2, b4, b5, T(547), T(1922), T(-494), T(2843), T(-1642), T(267), eps);
+    const T e2 = indicator<T>(b1, b2, b4, T(267), T(-1642), T(-494), T(2843), T(1922), T(547), eps);
+    const T e3 = indicator<T>(b0, b1, b2, T(547), T(-3882), T(4642), T(7043), T(-17246), T(11003), eps);
+    const T r = weno_combine<T>(e0 * e0, e1 * e1, e2 * e2, e3 * e3, q0, q1, q2, q3);
+    return fma_t<T>(tv12, r, tv * a3);
 }
 
 // -i [H, rho] for a 2x2 Hermitian H = [[h_ee, h_ex], [h_ex^*, h_xx]] given by
@@ -324,11 +340,11 @@ __device__ __forceinline__ T interface_flux(T u0, T u1, T u2, T u3, T u4, T u5, 
         return fd_ko_flux<T>(u0, u1, u2, u3, cv, ko[0], ko[1]);
     } else if constexpr (SCHEME == 2) {
         return fd_ko3_flux<T>(u0, u1, u2, u3, u4, u5, cv, ko[0], ko[1], ko[2]);
-    } else if constexpr (MIX) {
-        return tv * weno7_flux<T>(vpos ? u0 : u7, vpos ? u1 : u6, vpos ? u2 : u5, vpos ? u3 : u4, vpos ? u4 : u3,
-                                  vpos ? u5 : u2, vpos ? u6 : u1, epsv);
+    } else if constexpr (MIX) {  // cv = v/12
+        return weno7_flux<T>(vpos ? u0 : u7, vpos ? u1 : u6, vpos ? u2 : u5, vpos ? u3 : u4, vpos ? u4 : u3,
+                             vpos ? u5 : u2, vpos ? u6 : u1, epsv, tv, cv);
     } else {
-        return tv * weno7_flux<T>(u0, u1, u2, u3, u4, u5, u6, epsv);
+        return weno7_flux<T>(u0, u1, u2, u3, u4, u5, u6, epsv, tv, cv);
     }
 }
 
@@ -357,12 +373,13 @@ __device__ __forceinline__ GroupGeom group_geom(const InstDesc &d, int task, int
 }
 
 // Everything one row needs from memory, loaded one row ahead of its use.
-template <typename TI, int NC>
+template <typename TI, int NC, bool CE>
 struct RowBuf {
     TI nw[NC];        // the window row entering with this row (the look-ahead row)
     double a0[NC];    // y (or acc in stage 4) of the produced row
     double S[kMomQ];  // summed moment partials of the input row
     double pv[2];     // or, with one row group per wave, its lane's two partials
+    double ce[CE ? NC : 1];  // CE: the exact FP64 stage input at the produced row
 };
 
 // The moment partials of an input row come from nparts = 2 vchunks producer
@@ -431,10 +448,14 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     constexpr int AH = R - 1 - CTR;  // look-ahead distance
     constexpr int NC = 4;                   // components of one species
     constexpr bool AUX0 = STAGE != 0;       // y, or acc in stage 4
-    // The window keeps the stage input as stored; the FP32 form rounds it to
-    // FP32 where the right-hand side consumes it, and its stage combine uses
-    // the exact FP64 centre value.
-    using Buf = RowBuf<TI, NC>;
+    // The window keeps the stage input as the right-hand side sees it: FP64 in
+    // the FP64 form; in the FP32 form rounded to FP32 once, as the row enters
+    // (the look-ahead row is read as stored).  The FP32 form's stage combine
+    // needs the exact FP64 centre value of an FP64 input, which is then read
+    // again, one step ahead, from the caches (CE).
+    using TW = typename std::conditional<FORM == 1, float, TI>::type;
+    constexpr bool CE = FORM == 1 && !IN32;
+    using Buf = RowBuf<TI, NC, CE>;
 
     const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
     const int sp = q.sp, jl = q.jl;
@@ -526,6 +547,16 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
             if constexpr (AUX0) a0[c] = ld<double>(aux0b + (size_t)c * p64, off);
         }
     };
+    auto issue_centre = [&](int k, double (&ce)[CE ? NC : 1]) {
+        if constexpr (CE) {
+            const int r = start + dir * k;
+            int irow = min(max(r, 0), nz - 1);
+            if constexpr (WR) irow = __builtin_amdgcn_readfirstlane(irow);
+            const uint32_t off = (uint32_t)(irow * nv + jl) * 8u;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) ce[c] = ld<double>(inb + (size_t)c * pin, off);
+        }
+    };
     // the window row entering at step k
     auto issue_ahead = [&](int k, TI (&nw)[NC]) {
         const int r = start + dir * k;
@@ -540,17 +571,18 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     auto issue = [&](int k, Buf &b) {
         issue_ahead(k, b.nw);
         issue_side(k, b.a0, b.S, b.pv);
+        issue_centre(k, b.ce);
     };
 
-    TI w[NC][R - 1];  // carried window rows: w[.][m] is row r + dir (m - CTR)
+    TW w[NC][R - 1];  // carried window rows: w[.][m] is row r + dir (m - CTR)
     T fprev[NC];      // flux on the face behind the current row
 
     auto compute = [&](int k, const Buf &b) {
         const int r = start + dir * k;
         const bool row_in = WR || k < nrows;
         const int irow = min(r, nz - 1);
-        auto win = [&](int c, int m) -> TI {  // window row m of this step, as stored
-            return m < R - 1 ? w[c][m] : b.nw[c];
+        auto win = [&](int c, int m) -> TW {  // window row m of this step
+            return m < R - 1 ? w[c][m] : (TW)b.nw[c];
         };
         const double(&a0)[NC] = b.a0;
         const double(&S0)[kMomQ] = b.S;
@@ -590,7 +622,10 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         const bool on = row_in && q.lane_on;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double centre = (double)win(c, CTR);  // exact stage input (FP64 except Y3)
+            // exact stage input (FP64 except Y3 of the FP32 form)
+            double centre;
+            if constexpr (CE) centre = b.ce[c];
+            else centre = (double)win(c, CTR);
             if constexpr (STAGE == 0) {
                 o[c] = centre + hdt * kk[c];
             } else if constexpr (STAGE == 1) {
@@ -622,7 +657,11 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
 #pragma unroll
         for (int m = 0; m < R - 1; ++m) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) w[c][m] = m < R - 2 ? w[c][m + 1] : fresh_copy(b.nw[c]);
+            for (int c = 0; c < NC; ++c) {
+                if (m < R - 2) w[c][m] = w[c][m + 1];
+                else if constexpr (std::is_same<TW, TI>::value) w[c][m] = fresh_copy(b.nw[c]);
+                else w[c][m] = (TW)b.nw[c];  // the conversion writes a register of its own
+            }
         }
     };
 
@@ -635,7 +674,7 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         TI tmp[NC];
         load_row(wrap_row(start + dir * (m - CTR), nz), tmp);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) w[c][m] = tmp[c];
+        for (int c = 0; c < NC; ++c) w[c][m] = (TW)tmp[c];
     }
     Buf bufA, bufB;
     issue(0, bufA);

@@ -197,11 +197,11 @@ def test_kreiss_oliger_effect_on_box_profile(precision):
     assert np.abs(res[0.0] - exact).sum() > 2 * np.abs(res[0.1] - exact).sum()
 
 
-def _log2_or_nan(x):
+def _log2_or_nan(num, den):
     """log2 of a ratio of error differences; once both errors of a difference
-    sit at the saturated time-integration error the ratio can turn negative
-    (it carries no order there)."""
-    return math.log2(x) if x > 0 else float("nan")
+    sit at the saturated time-integration error the ratio can turn negative or
+    its denominator vanish (it carries no order there)."""
+    return math.log2(num / den) if den != 0 and num / den > 0 else float("nan")
 
 
 def test_fixed_dt_convergence_kappa():
@@ -225,7 +225,7 @@ def test_fixed_dt_convergence_kappa():
         # Appendix C's estimator of the spatial order from three errors at the
         # same dt, dz halving (r = 2): the constant time-integration error
         # cancels in the differences
-        alpha[scheme] = [_log2_or_nan((dps[i] - dps[i + 1]) / (dps[i + 1] - dps[i + 2])) for i in range(len(dps) - 2)]
+        alpha[scheme] = [_log2_or_nan(dps[i] - dps[i + 1], dps[i + 1] - dps[i + 2]) for i in range(len(dps) - 2)]
         print(f"scheme {scheme}: dP_max {['%.2e' % x for x in dps]}, kappa {['%.2f' % k for k in kappa[scheme]]}, "
               f"alpha {['%.2f' % k for k in alpha[scheme]]}")
     # FD + KO: spatial error dominates at every Nz, kappa ~ its order 3
