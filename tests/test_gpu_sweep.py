@@ -1,6 +1,8 @@
 """A seeded sweep over the options that combine: scheme, form, Kreiss-Oliger
 order, velocity grid, shape (ragged rows and bins, tiny grids), launch shape
-and fusion, each case against the FP64 oracle from a random nonlinear state.
+and path (single stages, fused stage pairs, the whole step in one launch,
+where the shape allows them), each case against the FP64 oracle from a
+random nonlinear state.
 Bars as everywhere: FP64 form within 1e-12 max-abs, FP32 form within 1e-5
 max-abs (the state is O(1) and a few steps are taken)."""
 import numpy as np
@@ -15,6 +17,7 @@ pytestmark = pytest.mark.gpu
 
 def _cases(n=96, seed=2026):
     rng = np.random.default_rng(seed)
+    rng_path = np.random.default_rng(seed + 1)  # the path: 0 single stages, 1 fused pairs, 2 whole step
     out = []
     for i in range(n):
         scheme = int(rng.integers(0, 2))
@@ -25,9 +28,12 @@ def _cases(n=96, seed=2026):
         r = int(rng.integers(1, 4))
         nzmin = 9 if scheme == wl.FV_WENO7 else max(5, 2 * r + 1)
         nz = int(rng.integers(nzmin, 160))
-        out.append(dict(i=i, scheme=scheme, quad=quad, nv=nv, nz=nz, ko_order=r,
-                        precision=int(rng.integers(0, 2)), seg=int(rng.choice([0, 1, 2, 5, 13, 64])),
-                        fusion=bool(rng.integers(0, 2)), steps=int(rng.integers(1, 6)),
+        precision = int(rng.integers(0, 2))
+        seg = int(rng.choice([0, 1, 2, 5, 13, 64]))
+        rng.integers(0, 2)  # a draw the earlier two-path version took here; kept so the other draws stay put
+        fusion = int(rng_path.integers(0, 3))
+        out.append(dict(i=i, scheme=scheme, quad=quad, nv=nv, nz=nz, ko_order=r, precision=precision, seg=seg,
+                        fusion=fusion, steps=int(rng.integers(1, 6)),
                         omega=float(rng.uniform(0, 0.5)), lam=float(rng.uniform(0, 1.0)),
                         alpha=float(rng.uniform(0.5, 1.1)), ko_eps=float(rng.choice([0.0, 0.1, 0.3])),
                         cfl=float(rng.uniform(0.1, 0.6))))
