@@ -265,6 +265,42 @@ def cpu_baseline(cosenu, w, budget_s):
     return cb, errs
 
 
+def cpu_baseline_per_config(budget_each: float):
+    """The FP64 oracle (all host threads) on a bounded sample of every
+    configuration, as cell-velocity-stage updates/s: the 512 x 32 case whole,
+    periodic z-slabs (same dz and dt) of the others, and slabs of the first
+    four instances of the 64-instance batch (their nv and schemes differ)."""
+    from oracle import oracle as o
+    from paper_2203_12866_amd import workloads as wl
+    out = {}
+
+    def slab_rate(w, budget):
+        r, _, _ = _oracle_sample(o, w, min(w["nz"], 16), 1)
+        rows = max(16, min(w["nz"], int(budget * r / (w["nv"] * 4.0)) // 16 * 16))
+        return _oracle_sample(o, w, rows, 1)[:2] + (rows,)
+
+    w1 = wl.small_fd(1)
+    r1, t1, _ = _oracle_sample(o, w1, w1["nz"], 2)
+    out["fd_ko_512x32"] = {"value": r1, "sample": f"2 RK4 steps of the whole 512x32 grid, {t1:.1f} s"}
+    for name, w in (("fd_ko_16384x128", wl.fd_16384x128(2, 0)), ("fv_weno7_65536x256", wl.fv_65536x256(3, 0)),
+                    ("fv_weno7_1048576x512", wl.fv_1m_x512(5, 0))):
+        r, t, rows = slab_rate(w, budget_each)
+        out[name] = {"value": r, "sample": f"1 RK4 step of a periodic {rows}x{w['nv']} z-slab, {t:.1f} s"}
+    upd = secs = 0.0
+    parts = []
+    for w in wl.batch_64(4)[:4]:
+        w = dict(w, precision=0)
+        r, t, rows = slab_rate(w, budget_each / 4.0)
+        upd += r * t
+        secs += t
+        parts.append(f"{rows}x{w['nv']} {'FD' if w['scheme'] == 0 else 'WENO7'}")
+    out["batch_64"] = {"value": upd / secs, "sample": "1 RK4 step of periodic z-slabs of instances 0-3 ("
+                       + ", ".join(parts) + f"), {secs:.1f} s"}
+    for v in out.values():
+        v["unit"] = "cell·v·stage updates/s"
+    return out
+
+
 # kernel variants of a batch, in the order cosenu_batch_autotune reports them
 BATCH_VARIANTS = ["fd_nv<=32", "fd_nv>32", "weno7_nv<=32", "weno7_nv>32", "fd_ko3_nv<=32", "fd_ko3_nv>32",
                   "fd_pairs_w2", "fd_pairs_w4", "fd_pairs_w6", "fd_pairs_w8",
@@ -418,6 +454,8 @@ def main():
                     help="0 single stages, 1 fused (the autotuner picks the path), 2 the whole step in one launch "
                          "where supported (with --seg-rows, which skips the autotuner)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--cpu-budget-per-config", type=float, default=3.0,
+                    help="seconds of oracle work per configuration for cpu_baseline.per_config (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB between device buffers six times (the reference for the HBM counters)")
     args = ap.parse_args()
@@ -504,6 +542,8 @@ def main():
         out["secondary"] = sec
     if not args.no_cpu_baseline:
         cb, errs = cpu_baseline(cosenu, WORKLOADS[args.workload](0), args.cpu_budget)
+        if args.cpu_budget_per_config > 0 and args.workload == DEFAULT_WORKLOAD:
+            cb["per_config"] = cpu_baseline_per_config(args.cpu_budget_per_config)
         out["cpu_baseline"] = cb
         if errs is not None:
             out["error_vs_oracle"] = errs

@@ -373,13 +373,12 @@ __device__ __forceinline__ GroupGeom group_geom(const InstDesc &d, int task, int
 }
 
 // Everything one row needs from memory, loaded one row ahead of its use.
-template <typename TI, int NC, bool CE>
+template <typename TI, int NC>
 struct RowBuf {
     TI nw[NC];        // the window row entering with this row (the look-ahead row)
     double a0[NC];    // y (or acc in stage 4) of the produced row
     double S[kMomQ];  // summed moment partials of the input row
     double pv[2];     // or, with one row group per wave, its lane's two partials
-    double ce[CE ? NC : 1];  // CE: the exact FP64 stage input at the produced row
 };
 
 // The moment partials of an input row come from nparts = 2 vchunks producer
@@ -448,14 +447,13 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     constexpr int AH = R - 1 - CTR;  // look-ahead distance
     constexpr int NC = 4;                   // components of one species
     constexpr bool AUX0 = STAGE != 0;       // y, or acc in stage 4
-    // The window keeps the stage input as the right-hand side sees it: FP64 in
-    // the FP64 form; in the FP32 form rounded to FP32 once, as the row enters
-    // (the look-ahead row is read as stored).  The FP32 form's stage combine
-    // needs the exact FP64 centre value of an FP64 input, which is then read
-    // again, one step ahead, from the caches (CE).
-    using TW = typename std::conditional<FORM == 1, float, TI>::type;
-    constexpr bool CE = FORM == 1 && !IN32;
-    using Buf = RowBuf<TI, NC, CE>;
+    // The window keeps the stage input as stored; the FP32 form rounds it to
+    // FP32 where the right-hand side consumes it, and its stage combine uses
+    // the exact FP64 centre value.  (Keeping the window in FP32 and reading the
+    // exact centre again saves conversions but the re-read missed the L2: 1.32x
+    // the algorithmic bytes in fetches instead of 1.08x, for no time gained.)
+    using TW = TI;
+    using Buf = RowBuf<TI, NC>;
 
     const int nz = d.nz, nv = d.nv, vchunks = d.vchunks;
     const int sp = q.sp, jl = q.jl;
@@ -547,16 +545,6 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
             if constexpr (AUX0) a0[c] = ld<double>(aux0b + (size_t)c * p64, off);
         }
     };
-    auto issue_centre = [&](int k, double (&ce)[CE ? NC : 1]) {
-        if constexpr (CE) {
-            const int r = start + dir * k;
-            int irow = min(max(r, 0), nz - 1);
-            if constexpr (WR) irow = __builtin_amdgcn_readfirstlane(irow);
-            const uint32_t off = (uint32_t)(irow * nv + jl) * 8u;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) ce[c] = ld<double>(inb + (size_t)c * pin, off);
-        }
-    };
     // the window row entering at step k
     auto issue_ahead = [&](int k, TI (&nw)[NC]) {
         const int r = start + dir * k;
@@ -571,7 +559,6 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     auto issue = [&](int k, Buf &b) {
         issue_ahead(k, b.nw);
         issue_side(k, b.a0, b.S, b.pv);
-        issue_centre(k, b.ce);
     };
 
     TW w[NC][R - 1];  // carried window rows: w[.][m] is row r + dir (m - CTR)
@@ -622,10 +609,7 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         const bool on = row_in && q.lane_on;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            // exact stage input (FP64 except Y3 of the FP32 form)
-            double centre;
-            if constexpr (CE) centre = b.ce[c];
-            else centre = (double)win(c, CTR);
+            const double centre = (double)win(c, CTR);  // exact stage input (FP64 except Y3)
             if constexpr (STAGE == 0) {
                 o[c] = centre + hdt * kk[c];
             } else if constexpr (STAGE == 1) {
@@ -657,11 +641,7 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
 #pragma unroll
         for (int m = 0; m < R - 1; ++m) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                if (m < R - 2) w[c][m] = w[c][m + 1];
-                else if constexpr (std::is_same<TW, TI>::value) w[c][m] = fresh_copy(b.nw[c]);
-                else w[c][m] = (TW)b.nw[c];  // the conversion writes a register of its own
-            }
+            for (int c = 0; c < NC; ++c) w[c][m] = m < R - 2 ? w[c][m + 1] : fresh_copy(b.nw[c]);
         }
     };
 
