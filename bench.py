@@ -420,6 +420,7 @@ def run_workload(cosenu, torch, name, steps, warmup, seg, stage_steps, fused):
             "bytes_per_update": r["info"]["bytes_per_step"] / (cells * 4.0),
             "roofline": roof,
             "seg_rows": r["seg"],
+            "waves_per_workgroup": r["info"]["waves_per_workgroup"],
         }
     return {
         "config": {"workload": name, "nz": w["nz"], "nv": w["nv"], "L": w["L"], "cfl": w["cfl"],
@@ -506,7 +507,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64acc",
         "data": "synthetic",
-        "config": dict(main_run["config"], form="FP32 stencils, FP64 moments/commutator/RK4", seg_rows=head["seg"]),
+        "config": dict(main_run["config"], form="FP32 stencils, FP64 moments/commutator/RK4", seg_rows=head["seg"],
+                       waves_per_workgroup=hf["waves_per_workgroup"]),
         "modelled_gbps": hf["modelled_gbps"],
         "bytes_per_update": hf["bytes_per_update"],
         "roofline": roof,

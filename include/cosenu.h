@@ -150,10 +150,6 @@ typedef struct {
     double bytes_per_step;   /* algorithmic HBM bytes of one RK4 step          */
     int32_t launches_per_step; /* 4 single stages, or 2 fused stage pairs      */
     int32_t waves_per_workgroup; /* of the single-stage launches (1, 2 or 4)  */
-    int32_t segments_per_workgroup; /* of the single-stage launches with more
-                                     * than 32 bins: 1 (the waves take the
-                                     * chunks of one segment), 2 or 4 (the
-                                     * waves take neighbouring segments)      */
 } cosenu_info_t;
 
 /* Fills *p with the paper's fiducial values (Sec. 5): nz = 512, nv = 32,
@@ -240,14 +236,11 @@ int cosenu_time_steps(cosenu_sim *s, int64_t nsteps, double *ms);
 int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage);
 
 /* Picks the launch shape by timing whole RK4 steps on the handle's buffers:
- * the segment length of the fused stage pairs and of the whole step in one
- * launch (where the shape allows them and fusion is on); the segment length,
- * the waves per workgroup (1, 2 or 4) and, with more than 32 bins, the
- * segments per workgroup (1, 2 or 4: waves of neighbouring segments side by
- * side share their halo rows in L2) of the single stages; and the fastest of
- * the paths (the fused ones recompute the halos of their intermediate stages
- * on chip; single stages re-read their stencil halo from the caches).  The
- * state, its moments and all later results
+ * the segment length of the fused stage pairs (where the shape allows them and
+ * fusion is on), the segment length and the waves per workgroup (1, 2 or 4) of
+ * the single stages, and the faster of the two paths (fused pairs recompute a
+ * two-row halo of the intermediate stage on chip; single stages re-read their
+ * stencil halo from the caches).  The state, its moments and all later results
  * are unchanged (results do not depend on launch shapes).  The choice is
  * cached per device and (kernel variant, precision, nv, nz bucket) for the
  * process, and handles created later start from it; if the environment

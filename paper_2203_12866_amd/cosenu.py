@@ -75,7 +75,6 @@ class Info(ctypes.Structure):
         ("seg_rows", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("v_chunks", ctypes.c_int32),
         ("blocks_per_stage", ctypes.c_int32), ("bytes_per_step", ctypes.c_double),
         ("launches_per_step", ctypes.c_int32), ("waves_per_workgroup", ctypes.c_int32),
-        ("segments_per_workgroup", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

@@ -298,7 +298,6 @@ void fill_desc_constants(const cosenu_params &p, InstDesc &d) {
     d.weno_eps = p.weno_eps;
     d.ps = (size_t)p.nz * p.nv + kPlanePad;
     d.wpb = kWavesPerBlock;
-    d.spb = 1;
     set_shape(d, default_seg_rows(p.nz, p.nv));
 }
 
@@ -390,8 +389,7 @@ const char *tune_file() {
     return f && *f ? f : nullptr;
 }
 
-// One line per entry: device scheme form nv bucket seg_pairs seg_quad seg_single wpb path spb
-// (a line without the last column has spb 0: segments per workgroup not tuned).
+// One line per entry: device scheme form nv bucket seg_pairs seg_quad seg_single wpb path.
 void load_tune_file_locked() {
     g_tune_loaded = true;
     const char *path = tune_file();
@@ -399,16 +397,14 @@ void load_tune_file_locked() {
     FILE *f = std::fopen(path, "r");
     if (!f) return;
     char dev[128];
-    int scheme, form, nv, bucket, sp, sq, ss, wpb, pth, spb;
+    int scheme, form, nv, bucket, sp, sq, ss, wpb, pth;
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
-        spb = 0;
-        const int n = std::sscanf(line, "%127s %d %d %d %d %d %d %d %d %d %d", dev, &scheme, &form, &nv, &bucket, &sp,
-                                  &sq, &ss, &wpb, &pth, &spb);
-        if (n != 10 && n != 11) continue;
-        if (sp < 0 || sq < 0 || ss < 0 || (wpb != 0 && wpb != 1 && wpb != 2 && wpb != 4) || pth < -1 || pth > 2 ||
-            (spb != 0 && spb != 1 && spb != 2 && spb != 4))
+        if (std::sscanf(line, "%127s %d %d %d %d %d %d %d %d %d", dev, &scheme, &form, &nv, &bucket, &sp, &sq, &ss,
+                        &wpb, &pth) != 10)
+            continue;
+        if (sp < 0 || sq < 0 || ss < 0 || (wpb != 0 && wpb != 1 && wpb != 2 && wpb != 4) || pth < -1 || pth > 2)
             continue;
         TuneEntry e;
         e.seg_pairs = sp;
@@ -416,7 +412,6 @@ void load_tune_file_locked() {
         e.seg_single = ss;
         e.wpb = wpb;
         e.path = pth;
-        e.spb = spb;
         g_tune_cache[std::string(dev) + " " + std::to_string(scheme) + " " + std::to_string(form) + " " +
                      std::to_string(nv) + " " + std::to_string(bucket)] = e;
     }
@@ -430,11 +425,10 @@ void save_tune_file_locked() {
     FILE *f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
     std::fprintf(f, "# cosenu launch-shape cache: device scheme form nv nz_bucket seg_pairs seg_whole_step "
-                    "seg_single waves_per_workgroup path(0 single stages, 1 fused pairs, 2 whole step, -1 unknown) "
-                    "segments_per_workgroup\n");
+                    "seg_single waves_per_workgroup path(0 single stages, 1 fused pairs, 2 whole step, -1 unknown)\n");
     for (const auto &kv : g_tune_cache)
-        std::fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.seg_pairs, kv.second.seg_quad,
-                     kv.second.seg_single, kv.second.wpb, kv.second.path, kv.second.spb);
+        std::fprintf(f, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.seg_pairs, kv.second.seg_quad,
+                     kv.second.seg_single, kv.second.wpb, kv.second.path);
     const bool ok = std::fclose(f) == 0;
     if (!ok || std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
 }
@@ -748,11 +742,6 @@ int cosenu_create(const cosenu_params *p, cosenu_sim **out) try {
         const TuneEntry e = tuned_entry(s->d.scheme, p->precision, p->nz, p->nv);
         s->tuned_path = e.path;
         if (e.wpb > 0) s->d.wpb = e.wpb;
-        if (e.spb > 0) s->d.spb = e.spb;
-        if (!launch_shape_ok(s->d)) {  // a cache line whose shape this problem cannot take
-            s->d.wpb = kWavesPerBlock;
-            s->d.spb = 1;
-        }
         const int path = path_of(s);
         const int tuned = path == 2 ? e.seg_quad : path == 1 ? e.seg_pairs : e.seg_single;
         if (tuned > 0) set_shape(s->d, tuned);
@@ -901,7 +890,6 @@ int cosenu_info(cosenu_sim *s, cosenu_info_t *out) try {
     out->bytes_per_step = bytes_per_step_of(s);
     out->launches_per_step = launches_per_step(s);
     out->waves_per_workgroup = s->d.wpb;
-    out->segments_per_workgroup = s->d.lr_log2 == 6 ? s->d.spb : 1;
     return COSENU_OK;
 } COSENU_ABI_CATCH(s ? &s->err : nullptr)
 
@@ -1003,15 +991,12 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) try {
     // the fused pairs overwrite the moments of the current state, which are
     // rebuilt afterwards from the state with the producer's own arithmetic.
     //
-    // Search: the segment length of the whole step and of the fused pairs
-    // (where the shape allows them and fusion is on); the segment length of
-    // the single stages with 4 waves per workgroup, then other workgroup
-    // shapes at that length (2 or 4 segments per workgroup with one row group
-    // per wave, 1 or 2 waves per workgroup), with the length swept again for a
-    // shape of several segments per workgroup; then the fastest path.  Segment
-    // lengths are about sqrt(2) apart: the workgroup count of the fused pairs
-    // (one per segment) has to land just under a whole number of resident
-    // rounds.
+    // Search: the segment length of the fused pairs (where the shape allows
+    // them and fusion is on), the segment length of the single stages with 4
+    // waves per workgroup, then 1 and 2 waves per workgroup at that length,
+    // then the faster of the two paths.  Segment lengths are about sqrt(2)
+    // apart: the workgroup count of the fused pairs (one per segment) has to
+    // land just under a whole number of resident rounds.
     const int cands[] = {4, 6, 8, 11, 16, 22, 32, 45, 64, 90, 128, 181, 256};
     const InstDesc keep = s->d;
     const bool try_pairs = s->fusion != 0 && pair_supported(s->d);
@@ -1073,13 +1058,12 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) try {
         return COSENU_EDEVICE;
     };
     // the fastest segment length of one path at the given waves per workgroup
-    auto sweep = [&](int path, int wpb, int spb, int *seg_out, double *ms_out) -> bool {
+    auto sweep = [&](int path, int wpb, int *seg_out, double *ms_out) -> bool {
         *ms_out = 1e300;
         for (int c : cands) {
             if (c > keep.nz) break;
             InstDesc d = keep;
             d.wpb = wpb;
-            d.spb = spb;
             set_shape(d, c);
             double ms;
             if (!time_step(d, path, &ms)) return false;
@@ -1092,32 +1076,19 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) try {
     };
     TuneEntry e = tuned_entry(keep.scheme, s->prm.precision, s->prm.nz, s->prm.nv);
     double ms_pairs = 1e300, ms_single = 1e300, ms_quad = 1e300;
-    int seg_pairs = keep.seg, seg_single = keep.seg, seg_quad = keep.seg, wpb = kWavesPerBlock, spb = 1;
-    if (try_quad && !sweep(2, kWavesPerBlock, 1, &seg_quad, &ms_quad)) return fail();
-    if (try_pairs && !sweep(1, kWavesPerBlock, 1, &seg_pairs, &ms_pairs)) return fail();
-    if (!sweep(0, kWavesPerBlock, 1, &seg_single, &ms_single)) return fail();
-    const int shapes[][2] = {{4, 2}, {4, 4}, {2, 1}, {2, 2}, {1, 1}};  // waves, segments per workgroup
-    for (const auto &sh : shapes) {
+    int seg_pairs = keep.seg, seg_single = keep.seg, seg_quad = keep.seg, wpb = kWavesPerBlock;
+    if (try_quad && !sweep(2, kWavesPerBlock, &seg_quad, &ms_quad)) return fail();
+    if (try_pairs && !sweep(1, kWavesPerBlock, &seg_pairs, &ms_pairs)) return fail();
+    if (!sweep(0, kWavesPerBlock, &seg_single, &ms_single)) return fail();
+    for (int w : {2, 1}) {
         InstDesc d = keep;
-        d.wpb = sh[0];
-        d.spb = sh[1];
+        d.wpb = w;
         set_shape(d, seg_single);
-        if (!launch_shape_ok(d) || (sh[1] > 1 && d.lr_log2 != 6)) continue;
         double ms;
         if (!time_step(d, 0, &ms)) return fail();
         if (ms < ms_single) {
             ms_single = ms;
-            wpb = sh[0];
-            spb = sh[1];
-        }
-    }
-    if (spb > 1) {
-        int seg2 = seg_single;
-        double ms2;
-        if (!sweep(0, wpb, spb, &seg2, &ms2)) return fail();
-        if (ms2 < ms_single) {
-            ms_single = ms2;
-            seg_single = seg2;
+            wpb = w;
         }
     }
     int path = 0;
@@ -1129,13 +1100,11 @@ int cosenu_autotune(cosenu_sim *s, int32_t *seg_rows) try {
     if (try_quad && ms_quad <= best) path = 2;
     e.seg_single = seg_single;
     e.wpb = wpb;
-    e.spb = spb;
     if (try_pairs) e.seg_pairs = seg_pairs;
     if (try_quad) e.seg_quad = seg_quad;
     if (try_pairs || try_quad) e.path = path;
     s->d = keep;
     s->d.wpb = wpb;
-    s->d.spb = spb;
     if (try_pairs || try_quad) s->tuned_path = path;
     set_shape(s->d, path == 2 ? seg_quad : path == 1 ? seg_pairs : seg_single);
     set_parity(s, s->parity);  // the moments of the state live where the chosen path keeps them

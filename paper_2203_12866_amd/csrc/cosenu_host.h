@@ -46,7 +46,6 @@ struct TuneEntry {
     int seg_quad = 0;    // whole step in one launch: rows per segment
     int seg_single = 0;  // single stages: rows per segment
     int wpb = 0;         // single stages: waves per workgroup (1, 2 or 4)
-    int spb = 0;         // single stages with one row group per wave: segments per workgroup (1, 2 or 4)
     int path = -1;       // the fastest full step: 0 single stages, 1 fused pairs, 2 whole step, -1 not compared
 };
 TuneEntry tuned_entry(int scheme, int form, int nz, int nv);

@@ -37,8 +37,6 @@ struct InstDesc {
     int32_t tps;       // stage tasks per species: nrowtasks padded to a multiple of the groups per wave
     int32_t ntasks;    // stage tasks: 2 * tps (neutrinos, then antineutrinos)
     int32_t wpb;       // waves per workgroup of the single-instance stage and moment kernels: 1, 2 or 4
-    int32_t spb;       // with one row group per wave, segments per workgroup: 1 (consecutive tasks), 2 or 4
-                       // (wpb / spb chunks of each; spb divides wpb and wpb / spb divides vchunks)
     double dz_inv;     // 1 / dz
     double dt;
     double mudv;       // mu * dv
@@ -107,8 +105,6 @@ hipError_t launch_init_state(const InstDesc &d, double L, double amp, double wid
 // per row and chunk [nz][vchunks][8]: dv sum D_q and dv sum v D_q, q = ee, xx, Re ex, Im ex
 hipError_t launch_moments_out(const InstDesc &d, double *out, int blocks, hipStream_t st);
 
-// whether d.wpb and d.spb form a launch shape the stage and moment kernels take
-bool launch_shape_ok(const InstDesc &d);
 // number of workgroups covering all stage tasks (d.wpb waves each) / all
 // (segment, chunk) tasks (kWavesPerBlock waves each)
 int blocks_for(const InstDesc &d);

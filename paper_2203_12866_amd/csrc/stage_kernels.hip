@@ -1372,43 +1372,17 @@ constexpr int kMinWavesPerSimd = SCHEME == 0 ? (WR ? 4 : 3) : (WR ? 3 : 2);
 // Single-instance launches: workgroups of d.wpb waves (1, 2 or 4, a launch
 // shape the autotuner picks), with d.wpb wave scratches of dynamic LDS for the
 // wave-row moment reduction.
-// With one row group per wave, a workgroup's waves take either consecutive
-// tasks (d.spb = 1: the chunks of one segment) or d.spb consecutive segments of
-// d.wpb / d.spb chunks each: then the waves of neighbouring segments, which
-// reach their shared halo rows at the same time, run side by side on one CU
-// and the second read of those rows can find them in L2.  Returns the wave's
-// task, or -1 for a wave past the last one.  The grid is blocks_for(d).
-__device__ __forceinline__ int wave_row_task(const InstDesc &d, int lb, int w) {
-    if (d.spb == 1) {
-        const int task = lb * d.wpb + w;
-        return task < d.ntasks ? task : -1;
-    }
-    const int cpb = d.wpb / d.spb;       // chunks per workgroup, a divisor of vchunks
-    const int ncg = d.vchunks / cpb;     // chunk groups per segment group
-    const int per_sp = (d.nseg + d.spb - 1) / d.spb * ncg;
-    const int sp = lb >= per_sp ? 1 : 0;
-    const int r = lb - sp * per_sp;
-    const int segi = r / ncg * d.spb + w % d.spb;
-    if (r >= per_sp || segi >= d.nseg) return -1;
-    return sp * d.tps + segi * d.vchunks + (r % ncg) * cpb + w / d.spb;
-}
-
 template <int SCHEME, int FORM, int STAGE, bool WR>
 __global__ __launch_bounds__(kWave *kWavesPerBlock, (kMinWavesPerSimd<SCHEME, WR>)) void stage_kernel(InstDesc d) {
     extern __shared__ __align__(16) double stage_pool[];
     const int lb = xcd_block(blockIdx.x, gridDim.x, (STAGE & 1) != 0);
+    const int wave = __builtin_amdgcn_readfirstlane(lb * d.wpb + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & (kWave - 1);
-    if constexpr (WR) {
-        const int task = __builtin_amdgcn_readfirstlane(wave_row_task(d, lb, (int)(threadIdx.x >> 6)));
-        if (task < 0) return;  // whole wave idle (uniform)
-        stage_group<SCHEME, FORM, STAGE, true>(d, task, lane, wave_lds<true>(stage_pool));
-    } else {
-        const int wave = __builtin_amdgcn_readfirstlane(lb * d.wpb + (int)(threadIdx.x >> 6));
-        const int G = kWave >> d.lr_log2;
-        const int task = wave * G + (lane >> d.lr_log2);
-        if (wave * G >= d.ntasks) return;  // whole wave idle (uniform)
-        stage_group<SCHEME, FORM, STAGE, false>(d, task, lane & ((1 << d.lr_log2) - 1), nullptr);
-    }
+    const int G = kWave >> d.lr_log2;
+    const int task = wave * G + (lane >> d.lr_log2);
+    if (wave * G >= d.ntasks) return;  // whole wave idle (uniform)
+    if constexpr (WR) stage_group<SCHEME, FORM, STAGE, true>(d, wave, lane, wave_lds<true>(stage_pool));
+    else stage_group<SCHEME, FORM, STAGE, false>(d, task, lane & ((1 << d.lr_log2) - 1), nullptr);
 }
 
 template <int FORM, bool WR>
@@ -1416,18 +1390,13 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void moments_init_kernel(Ins
     extern __shared__ __align__(16) double stage_pool[];
     double *pool = stage_pool;
     const int lb = xcd_block(blockIdx.x, gridDim.x, false);
+    const int wave = __builtin_amdgcn_readfirstlane(lb * d.wpb + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & (kWave - 1);
-    if constexpr (WR) {
-        const int task = __builtin_amdgcn_readfirstlane(wave_row_task(d, lb, (int)(threadIdx.x >> 6)));
-        if (task < 0) return;
-        moments_group<FORM, true>(d, task, lane, wave_lds<true>(pool));
-    } else {
-        const int wave = __builtin_amdgcn_readfirstlane(lb * d.wpb + (int)(threadIdx.x >> 6));
-        const int G = kWave >> d.lr_log2;
-        const int task = wave * G + (lane >> d.lr_log2);
-        if (wave * G >= d.ntasks) return;
-        moments_group<FORM, false>(d, task, lane & ((1 << d.lr_log2) - 1), nullptr);
-    }
+    const int G = kWave >> d.lr_log2;
+    const int task = wave * G + (lane >> d.lr_log2);
+    if (wave * G >= d.ntasks) return;
+    if constexpr (WR) moments_group<FORM, true>(d, wave, lane, wave_lds<true>(pool));
+    else moments_group<FORM, false>(d, task, lane & ((1 << d.lr_log2) - 1), nullptr);
 }
 
 // Batched launch: a fixed grid of waves walks the wave-task list round-robin
@@ -1539,8 +1508,6 @@ __global__ __launch_bounds__(kWave * (1 << PLOG), 3) void batch_pair_kernel(cons
 int groups_per_wave(const InstDesc &d) { return kWave >> d.lr_log2; }
 
 int blocks_for(const InstDesc &d) {
-    // one row group per wave, d.spb segments per workgroup
-    if (d.lr_log2 == 6 && d.spb > 1) return 2 * ((d.nseg + d.spb - 1) / d.spb) * (d.vchunks / (d.wpb / d.spb));
     const int G = groups_per_wave(d);
     const int waves = (d.ntasks + G - 1) / G;
     return (waves + d.wpb - 1) / d.wpb;
@@ -1601,21 +1568,15 @@ hipError_t launch_batch_w(const InstDesc *dd, const WaveTask *tk, int nwt, int s
 }
 }  // namespace
 
-bool launch_shape_ok(const InstDesc &d) {
-    if (d.wpb != 1 && d.wpb != 2 && d.wpb != 4) return false;
-    if (d.lr_log2 != 6 || d.spb == 1) return true;  // spb only shapes the kernels with one row group per wave
-    return (d.spb == 2 || d.spb == 4) && d.wpb % d.spb == 0 && d.vchunks % (d.wpb / d.spb) == 0;
-}
-
 hipError_t launch_stage(const InstDesc &d, int stage, int blocks, hipStream_t st) {
-    if (!launch_shape_ok(d)) return hipErrorInvalidValue;
+    if (d.wpb != 1 && d.wpb != 2 && d.wpb != 4) return hipErrorInvalidValue;
     const dim3 grid(blocks), block(kWave * d.wpb);
     return d.lr_log2 == 6 ? launch_stage_w<true>(d, stage, grid, block, st)
                           : launch_stage_w<false>(d, stage, grid, block, st);
 }
 
 hipError_t launch_moments_init(const InstDesc &d, int blocks, hipStream_t st) {
-    if (!launch_shape_ok(d)) return hipErrorInvalidValue;
+    if (d.wpb != 1 && d.wpb != 2 && d.wpb != 4) return hipErrorInvalidValue;
     const dim3 grid(blocks), block(kWave * d.wpb);
     const size_t shm = stage_shm_bytes(d);
     const bool wr = d.lr_log2 == 6;

@@ -4,11 +4,9 @@
   creates the same problem starts with the same launch shape (path, segment
   length, waves per workgroup) and reaches the same state bit for bit.
 * Shapes forced through the cache file (single stages instead of fused pairs,
-  1 or 2 waves per workgroup, 2 or 4 segments per workgroup, odd segment
-  lengths), for FD with wave rows, FD with row groups (nv <= 32) and WENO7,
-  give states bitwise equal to the default shapes' (results do not depend on
-  the launch shape); a cached workgroup shape the problem cannot take (chunks
-  per workgroup not dividing the chunks per row) falls back to the default.
+  1 or 2 waves per workgroup, odd segment lengths), for FD with wave rows,
+  FD with row groups (nv <= 32) and WENO7, give states bitwise equal to the
+  default shapes' (results do not depend on the launch shape).
 Every process here runs alone, one after the other.
 """
 import json
@@ -70,51 +68,42 @@ def test_cache_file_is_reused_by_a_second_process(tmp_path):
     lines = [ln for ln in open(cache) if not ln.startswith("#")]
     assert len(lines) == 1, lines
     f = lines[0].split()
-    assert f[1:5] == ["0", "1", "128", str(_bucket(1024))] and len(f) == 11
+    assert f[1:5] == ["0", "1", "128", str(_bucket(1024))] and len(f) == 10
     info_b, yb = _child(w, False, 7, str(tmp_path / "b.npy"), cache)
     print(f"tuned: {lines[0].strip()}; first process {info_a}")
-    for k in ("seg_rows", "launches_per_step", "waves_per_workgroup", "segments_per_workgroup"):
+    for k in ("seg_rows", "launches_per_step", "waves_per_workgroup"):
         assert info_a[k] == info_b[k], k
     assert np.array_equal(ya, yb)
     assert np.array_equal(ya, _solo(w, 7))
 
 
 @pytest.mark.parametrize("case", [
-    # (workload, forced entry: seg_pairs seg_whole_step seg_single wpb path spb, expected wpb spb)
-    (dict(nz=1024, nv=128, L=100.0), (0, 0, 5, 1, 0, 0), (1, 1)),         # FD, single stages instead of fusion
-    (dict(nz=1024, nv=128, L=100.0), (7, 0, 9, 2, 1, 0), None),           # FD, fused pairs at an odd segment
-    (dict(nz=1024, nv=128, L=100.0), (0, 13, 9, 2, 2, 0), None),          # FD, the whole step in one launch
-    (dict(nz=1024, nv=128, L=100.0), (0, 0, 7, 4, 0, 2), (4, 2)),         # FD single stages, 2 segments x 2 chunks
-    (dict(nz=1000, nv=128, L=100.0), (0, 0, 11, 4, 0, 4), (4, 4)),        # 4 segments x 1 chunk, ragged last group
-    (dict(nz=300, nv=20, L=30.0), (0, 0, 3, 1, -1, 0), (1, 1)),           # FD row groups (nv <= 32)
-    (dict(nz=200, nv=96, L=20.0, scheme=wl.FV_WENO7, omega=0.1), (0, 0, 3, 2, -1, 2), (2, 2)),  # WENO7 wave rows
-    (dict(nz=203, nv=256, L=20.0, scheme=wl.FV_WENO7, omega=0.1), (0, 0, 11, 4, -1, 4), (4, 4)),
-    (dict(nz=150, nv=512, L=15.0, scheme=wl.FV_WENO7, omega=0.1, precision=wl.FP32_ACC64), (0, 0, 8, 4, -1, 4),
-     (4, 4)),                                                                # FP32 form, 8 chunks per row
-    (dict(nz=190, nv=192, L=20.0, scheme=wl.FV_WENO7, lam=0.5), (0, 0, 6, 4, -1, 2), (4, 1)),  # 2 chunks per
-    # workgroup do not divide 3 chunks per row: the default shape
-    (dict(nz=200, nv=24, L=20.0, scheme=wl.FV_WENO7, lam=0.5), (0, 0, 11, 1, -1, 0), (1, 1)),  # WENO7 row groups
+    # (workload, forced entry: seg_pairs seg_whole_step seg_single wpb path)
+    (dict(nz=1024, nv=128, L=100.0), (0, 0, 5, 1, 0)),                 # FD, single stages instead of fusion
+    (dict(nz=1024, nv=128, L=100.0), (7, 0, 9, 2, 1)),                 # FD, fused pairs at an odd segment
+    (dict(nz=1024, nv=128, L=100.0), (0, 13, 9, 2, 2)),                # FD, the whole step in one launch
+    (dict(nz=300, nv=20, L=30.0), (0, 0, 3, 1, -1)),                   # FD row groups (nv <= 32)
+    (dict(nz=200, nv=96, L=20.0, scheme=wl.FV_WENO7, omega=0.1), (0, 0, 3, 2, -1)),  # WENO7 wave rows
+    (dict(nz=200, nv=24, L=20.0, scheme=wl.FV_WENO7, lam=0.5), (0, 0, 11, 1, -1)),   # WENO7 row groups
 ])
 def test_forced_shapes_from_cache_are_bitwise(tmp_path, case):
-    shape, (sp, sq, ss, wpb, path, spb), expect = case
+    shape, (sp, sq, ss, wpb, path) = case
     w = dict(wl.small_fd(3), **shape)
     cache = str(tmp_path / "tune.txt")
     # the device tag as the library writes it, from a tuning of a tiny problem
     _child(dict(wl.small_fd(1), nz=64, nv=64, L=10.0), True, 1, str(tmp_path / "t.npy"), cache)
     dev = [ln for ln in open(cache) if not ln.startswith("#")][0].split()[0]
     with open(cache, "w") as f:
-        f.write(f"{dev} {w['scheme']} {w['precision']} {w['nv']} {_bucket(w['nz'])} {sp} {sq} {ss} {wpb} {path}"
-                + (f" {spb}\n" if spb else "\n"))
+        f.write(f"{dev} {w['scheme']} {w['precision']} {w['nv']} {_bucket(w['nz'])} {sp} {sq} {ss} {wpb} {path}\n")
     info, got = _child(w, False, 9, str(tmp_path / "g.npy"), cache)
     nl = info["launches_per_step"]
-    print(f"forced {sp, sq, ss, wpb, path, spb}: {info}")
+    print(f"forced {sp, sq, ss, wpb, path}: {info}")
     if path == 2:
         assert nl == 1 and info["seg_rows"] == sq
     elif path == 1:
         assert nl == 2 and info["seg_rows"] == sp
     else:
-        assert nl == 4 and info["seg_rows"] == ss
-        assert (info["waves_per_workgroup"], info["segments_per_workgroup"]) == expect
+        assert nl == 4 and info["seg_rows"] == ss and info["waves_per_workgroup"] == wpb
     assert np.array_equal(got, _solo(w, 9))
 
 
