@@ -405,8 +405,13 @@ def run_workload(cosenu, torch, name, steps, warmup, seg, stage_steps, fused):
     for form, r in res.items():
         nl = r["launches"]
         suffix = {1: "/whole", 2: "/pairs", 4: ""}[nl]
+        traffic = measured_traffic(name, form + suffix)
         hbm = {"bound": "hbm", "achieved": r["achieved_gbps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-               "frac": r["achieved_gbps"] / PEAK_HBM_GBPS, "traffic": measured_traffic(name, form + suffix)}
+               "frac": r["achieved_gbps"] / PEAK_HBM_GBPS, "traffic": traffic}
+        if traffic:
+            # counter bytes per launch over this run's launch duration, and over the algorithmic bytes
+            hbm["traffic_gbps"] = traffic / r["launch_s"] / 1e9
+            hbm["traffic_over_algorithmic"] = traffic / (r["info"]["bytes_per_step"] / nl)
         alu = alu_roofline(name, form + suffix, r["launch_s"])
         if nl == 1 and alu is not None:
             # the whole step moves 32 B per update: VALU issue is its bound
