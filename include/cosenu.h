@@ -236,11 +236,12 @@ int cosenu_time_steps(cosenu_sim *s, int64_t nsteps, double *ms);
 int cosenu_time_stages(cosenu_sim *s, int64_t nsteps, double *ms_stage);
 
 /* Picks the launch shape by timing whole RK4 steps on the handle's buffers:
- * the segment length of the fused stage pairs (where the shape allows them and
- * fusion is on), the segment length and the waves per workgroup (1, 2 or 4) of
- * the single stages, and the faster of the two paths (fused pairs recompute a
- * two-row halo of the intermediate stage on chip; single stages re-read their
- * stencil halo from the caches).  The state, its moments and all later results
+ * the segment length of the whole step in one launch and of the fused stage
+ * pairs (where the shape allows them and fusion is on), the segment length and
+ * the waves per workgroup (1, 2 or 4) of the single stages, and the fastest of
+ * these paths (the fused ones recompute the halos of their intermediate stages
+ * on chip; single stages re-read their stencil halo from the caches).  The
+ * state, its moments and all later results
  * are unchanged (results do not depend on launch shapes).  The choice is
  * cached per device and (kernel variant, precision, nv, nz bucket) for the
  * process, and handles created later start from it; if the environment
