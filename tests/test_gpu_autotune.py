@@ -148,3 +148,28 @@ def test_batch_whole_steps_from_cache_are_bitwise(tmp_path):
     for i, w in enumerate(ws):
         ref = _solo(w, 7)
         assert np.array_equal(got[f"arr_{i}"], ref), i
+
+
+def test_cache_file_bad_lines_are_skipped(tmp_path):
+    """Lines the loader cannot use (too few fields, text, negative lengths,
+    waves per workgroup other than 1, 2, 4, an unknown path) are skipped; the
+    valid line for the shape is used, and a segment longer than the grid is
+    clamped to it; results stay bitwise the default's."""
+    cache = str(tmp_path / "tune.txt")
+    _child(dict(wl.small_fd(1), nz=64, nv=64, L=10.0), True, 1, str(tmp_path / "t.npy"), cache)
+    dev = [ln for ln in open(cache) if not ln.startswith("#")][0].split()[0]
+    w = dict(wl.small_fd(4), nz=300, nv=96, L=30.0, scheme=wl.FV_WENO7, omega=0.1)
+    b = _bucket(w["nz"])
+    key = f"{dev} {w['scheme']} {w['precision']} {w['nv']} {b}"
+    with open(cache, "w") as f:
+        f.write("# comment\n")
+        f.write("not a cache line at all\n")
+        f.write(f"{key} 0 0 5\n")                 # too few fields
+        f.write(f"{key} 0 0 -3 4 -1\n")           # negative segment length
+        f.write(f"{key} 0 0 5 3 -1\n")            # 3 waves per workgroup
+        f.write(f"{key} 0 0 5 2 7\n")             # unknown path
+        f.write(f"{key} 0 0 100000 2 -1\n")       # valid: a segment longer than the grid
+    info, got = _child(w, False, 6, str(tmp_path / "g.npy"), cache)
+    print(f"info {info}")
+    assert info["seg_rows"] == w["nz"] and info["waves_per_workgroup"] == 2
+    assert np.array_equal(got, _solo(w, 6))
