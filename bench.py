@@ -56,6 +56,7 @@ def kernel_hash() -> str:
 # instruction per 4 cycles per SIMD (16 lanes per cycle for FP64 and for
 # unpacked FP32), in billions of wave instructions per second
 PEAK_VALU_GINST = 256 * 4 * 2.4 / 4.0
+SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
 
 
 def profile_entry(workload: str, form: str):
@@ -87,8 +88,13 @@ def alu_roofline(workload: str, form: str, launch_s: float):
     if e is None or not e.get("valu_insts_per_launch"):
         return None
     g = e["valu_insts_per_launch"] / launch_s / 1e9
-    return {"achieved": g, "peak": PEAK_VALU_GINST, "unit": "G VALU wave64 instructions/s",
-            "frac": g / PEAK_VALU_GINST, "valu_insts_per_launch": e["valu_insts_per_launch"]}
+    out = {"achieved": g, "peak": PEAK_VALU_GINST, "unit": "G VALU wave64 instructions/s",
+           "frac": g / PEAK_VALU_GINST, "valu_insts_per_launch": e["valu_insts_per_launch"]}
+    if e.get("valu_issue_cycles_per_launch"):
+        # the same instructions priced per class (FP64 and transcendental instructions take more
+        # issue cycles than FP32 ones): the share of the chip's issue cycles the launch needs
+        out["priced_frac"] = e["valu_issue_cycles_per_launch"] / (SIMDS * CLOCK_HZ * launch_s)
+    return out
 
 
 def tracked(w, c0, c1):

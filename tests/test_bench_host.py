@@ -68,6 +68,11 @@ def test_valu_roofline_arithmetic(fake_root):
     assert a["frac"] == pytest.approx(1.0)
     a = bench.alu_roofline("w", "fp32acc", 4e-3)
     assert a["frac"] == pytest.approx(0.25)
+    assert "priced_frac" not in a
+    # priced issue cycles: 1024 SIMDs x 2.4e9 cycles/s x 1 ms = 2.4576e9 cycles is the whole chip
+    _write_profile(fake_root, bench.kernel_hash(),
+                   {"w/fp32acc": {"valu_insts_per_launch": 6.144e8, "valu_issue_cycles_per_launch": 1.2288e9}})
+    assert bench.alu_roofline("w", "fp32acc", 1e-3)["priced_frac"] == pytest.approx(0.5)
 
 
 def test_form_difference_whole_states_and_slabs():
