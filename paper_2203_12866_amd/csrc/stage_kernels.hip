@@ -449,9 +449,12 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
     constexpr bool AUX0 = STAGE != 0;       // y, or acc in stage 4
     // The window keeps the stage input as stored; the FP32 form rounds it to
     // FP32 where the right-hand side consumes it, and its stage combine uses
-    // the exact FP64 centre value.  (Keeping the window in FP32 and reading the
-    // exact centre again saves conversions but the re-read missed the L2: 1.32x
-    // the algorithmic bytes in fetches instead of 1.08x, for no time gained.)
+    // the exact FP64 centre value.  SPLIT (FP32 form, FP64 stage input): every
+    // row is rounded once as it enters an FP32 window, and only the rows from
+    // the centre to the look-ahead row stay in FP64 for the combine, in the
+    // same registers as a full FP64 window.  (Reading the exact centre again
+    // from memory instead missed the L2: 1.32x the algorithmic bytes.)
+    constexpr bool SPLIT = FORM == 1 && !IN32;
     using TW = TI;
     using Buf = RowBuf<TI, NC>;
 
@@ -561,15 +564,26 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         issue_side(k, b.a0, b.S, b.pv);
     };
 
-    TW w[NC][R - 1];  // carried window rows: w[.][m] is row r + dir (m - CTR)
+    // carried window rows: w[.][m] is row r + dir (m - CTR); with SPLIT, wf
+    // holds them in FP32 and wd the rows m = CTR .. R - 2 in FP64
+    constexpr int NW = SPLIT ? 1 : R - 1;
+    constexpr int ND = SPLIT ? R - 1 - CTR : 1;
+    TW w[NC][NW];
+    T wf[NC][SPLIT ? R - 1 : 1];
+    double wd[NC][ND];
     T fprev[NC];      // flux on the face behind the current row
 
     auto compute = [&](int k, const Buf &b) {
         const int r = start + dir * k;
         const bool row_in = WR || k < nrows;
         const int irow = min(r, nz - 1);
-        auto win = [&](int c, int m) -> TW {  // window row m of this step
-            return m < R - 1 ? w[c][m] : (TW)b.nw[c];
+        auto win = [&](int c, int m) -> TW {  // window row m of this step (exact; with SPLIT m >= CTR)
+            if constexpr (SPLIT) return m < R - 1 ? wd[c][m - CTR] : (TW)b.nw[c];
+            else return m < R - 1 ? w[c][m] : (TW)b.nw[c];
+        };
+        auto wlo = [&](int c, int m) -> T {  // window row m as the right-hand side sees it
+            if constexpr (SPLIT) return m < R - 1 ? wf[c][m] : (T)b.nw[c];
+            else return (T)win(c, m);
         };
         const double(&a0)[NC] = b.a0;
         const double(&S0)[kMomQ] = b.S;
@@ -577,7 +591,7 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         double adv[NC];  // flux differences times dir / dz
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            auto x = [&](int m) -> T { return m < R ? (T)win(c, REV ? R - 1 - m : m) : T(0); };
+            auto x = [&](int m) -> T { return m < R ? wlo(c, REV ? R - 1 - m : m) : T(0); };
             const T fnew = interface_flux<SCHEME, MIX, T>(x(0), x(1), x(2), x(3), x(4), x(5), x(6), x(7), tv, vpos, cv,
                                                           ce, epsv);
             adv[c] = ((double)fnew - (double)fprev[c]) * dzs;
@@ -599,7 +613,7 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         const double hi = mudv * A2;
         double u[NC], kk[NC];  // centre values as the right-hand side sees them
 #pragma unroll
-        for (int c = 0; c < NC; ++c) u[c] = (double)(T)win(c, CTR);
+        for (int c = 0; c < NC; ++c) u[c] = (double)wlo(c, CTR);
         minus_i_commutator(h3, hr, hi, u[0], u[1], u[2], u[3], kk[0], kk[1], kk[2], kk[3]);
 #pragma unroll
         for (int c = 0; c < NC; ++c) kk[c] -= adv[c];
@@ -638,10 +652,20 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         // registers so that the buffer's registers are free for the next load
         // into it (else the buffer would be moved, after waiting for its
         // loads, at the loop's back edge)
+        if constexpr (SPLIT) {
 #pragma unroll
-        for (int m = 0; m < R - 1; ++m) {
+            for (int c = 0; c < NC; ++c) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) w[c][m] = m < R - 2 ? w[c][m + 1] : fresh_copy(b.nw[c]);
+                for (int m = 0; m < R - 1; ++m) wf[c][m] = m < R - 2 ? wf[c][m + 1] : (T)b.nw[c];
+#pragma unroll
+                for (int j = 0; j < ND; ++j) wd[c][j] = j < ND - 1 ? wd[c][j + 1] : fresh_copy(b.nw[c]);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < R - 1; ++m) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) w[c][m] = m < R - 2 ? w[c][m + 1] : fresh_copy(b.nw[c]);
+            }
         }
     };
 
@@ -654,13 +678,23 @@ __device__ __forceinline__ void stage_body(const InstDesc &d, const GroupGeom &q
         TI tmp[NC];
         load_row(wrap_row(start + dir * (m - CTR), nz), tmp);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) w[c][m] = (TW)tmp[c];
+        for (int c = 0; c < NC; ++c) {
+            if constexpr (SPLIT) {
+                wf[c][m] = (T)tmp[c];
+                if (m >= CTR) wd[c][m - CTR] = (double)tmp[c];
+            } else {
+                w[c][m] = (TW)tmp[c];
+            }
+        }
     }
     Buf bufA, bufB;
     issue(0, bufA);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        auto y = [&](int m) -> T { return m == 0 ? (T)low[c] : (T)w[c][m - 1]; };
+        auto y = [&](int m) -> T {
+            if constexpr (SPLIT) return m == 0 ? (T)low[c] : wf[c][m - 1];
+            else return m == 0 ? (T)low[c] : (T)w[c][m - 1];
+        };
         auto x = [&](int m) -> T { return m < R ? y(REV ? R - 1 - m : m) : T(0); };
         fprev[c] = interface_flux<SCHEME, MIX, T>(x(0), x(1), x(2), x(3), x(4), x(5), x(6), x(7), tv, vpos, cv, ce,
                                                   epsv);
